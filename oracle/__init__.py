@@ -1,0 +1,142 @@
+"""CPU oracle for the Pade-based dimension-split ETD2RK scheme.
+
+TEST INFRASTRUCTURE ONLY.  The tests, the smoke check and the benchmark's
+CPU-baseline leg use this module; the product path never imports it.  It
+wraps ``etdo.c`` (plain C99, FP64 complex Thomas line solves, see that file's
+header for the formulas and their places in the paper) through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "etdo.c")
+_LIB = os.path.join(_HERE, "libetdo.so")
+
+_RXN = {
+    "none": 0, "linear": 1, "fisher": 2, "allen_cahn": 3, "ac_mms": 4,
+    "saturating": 5, "fhn_cubic": 6, "fhn_classic": 7,
+}
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("ncomp", ctypes.c_int),
+        ("kappa", ctypes.c_double * 2),
+        ("q", ctypes.c_double),
+        ("tau", ctypes.c_double),
+        ("rxn", ctypes.c_int),
+        ("rxn_param", ctypes.c_double * 8),
+        ("pade", ctypes.c_int),
+    ]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP over independent lines)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-D_DEFAULT_SOURCE",
+               "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd, cwd=_HERE)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER(_Problem)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.etdo_advance.argtypes = [P, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int]
+        L.etdo_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int]
+        L.etdo_reaction.argtypes = [P, ctypes.c_double, dp, dp]
+        L.etdo_poles.argtypes = [ctypes.c_int, dp, dp]
+        L.etdo_threads.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _struct(p) -> _Problem:
+    s = _Problem()
+    s.dim = p.dim
+    for d in range(3):
+        s.n[d] = p.n[d] if d < p.dim else 1
+        s.lo[d] = p.lo[d]
+        s.hi[d] = p.hi[d]
+    s.ncomp = p.ncomp
+    for c in range(p.ncomp):
+        s.kappa[c] = p.kappa[c]
+    s.q = p.q
+    s.tau = p.tau
+    s.rxn = _RXN[p.reaction]
+    for i, v in enumerate(p.params):
+        s.rxn_param[i] = v
+    s.pade = p.pade
+    return s
+
+
+def _f64(a: np.ndarray, shape) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.size != int(np.prod(shape)):
+        raise ValueError(f"field has {a.size} values, expected shape {shape}")
+    return a
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def advance(p, u: np.ndarray, nsteps: int, t0: float = 0.0, nthreads: int = 0) -> np.ndarray:
+    """Return U after nsteps steps of the scheme from time t0 (input untouched)."""
+    out = _f64(u, p.shape).copy()
+    rc = lib().etdo_advance(ctypes.byref(_struct(p)), _ptr(out), float(t0), int(nsteps), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle rejected the problem")
+    return out.reshape(p.shape)
+
+
+def apply(p, ell: int, d: int, g: np.ndarray, comp: int = 0, nthreads: int = 0) -> np.ndarray:
+    """Q_ell(tau A_d) g for one component (other components of the result are 0)."""
+    g = _f64(g, p.shape)
+    out = np.zeros(p.shape, dtype=np.float64)
+    rc = lib().etdo_apply(ctypes.byref(_struct(p)), int(ell), int(d), int(comp), _ptr(g), _ptr(out),
+                          int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return out
+
+
+def reaction(p, u: np.ndarray, t: float = 0.0) -> np.ndarray:
+    u = _f64(u, p.shape)
+    out = np.zeros(p.shape, dtype=np.float64)
+    rc = lib().etdo_reaction(ctypes.byref(_struct(p)), float(t), _ptr(u), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle rejected the problem")
+    return out
+
+
+def poles(pade: int):
+    """(poles, residues[l-1][k]) of the rational family."""
+    s = np.zeros(4)
+    r = np.zeros(12)
+    npl = lib().etdo_poles(int(pade), _ptr(s), _ptr(r))
+    sp = s[0:2 * npl:2] + 1j * s[1:2 * npl:2]
+    rr = (r[0:6 * npl:2] + 1j * r[1:6 * npl:2]).reshape(3, npl)
+    return sp, rr
+
+
+def threads(nthreads: int = 0) -> int:
+    return int(lib().etdo_threads(int(nthreads)))

@@ -1,0 +1,149 @@
+#!/usr/bin/env python
+"""Throughput of the spectral ETD2RK-DS step on one MI355X.
+
+A step is one full time step of the Pade-based dimension-split scheme (the
+z, y and fused x stages with both reaction evaluations) over the 3-D
+Fisher-KPP workload: 255^3 interior points, kappa = 0.005, q = 0.5,
+f = u(1-u), tau = 0.005, seeded sine-plus-Gaussian-bumps initial data.  The
+headline value is grid-point updates per second (n^3 * steps / wall seconds)
+in FP64; the reduced-precision variant is timed beside it and its relative L2
+distance to the FP64 result is reported.
+
+Prints one JSON line.  Options: --steps K (timed steps), --warmup W,
+--precision fp64|fp32, --reduced fp32|none, --cpu-steps S (oracle sample),
+--no-cpu-baseline, --n (grid size per direction).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point updates/sec (m^d x steps) at 3D m=255, FP64 vs reduced at <=1e-6"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+STAGE_NAMES = ("z_stage", "y_stage", "x_stage")
+# mode products per launch of each stage kind (3-D): z and y apply Q1 to two
+# fields (forward + back each), the fused x stage does five products
+PRODUCTS = (4, 4, 5)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--reduced", default="fp32", choices=["fp32", "none"])
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n", type=int, default=255)
+    return ap.parse_args()
+
+
+def timed_run(etd, torch, wl, precision, steps, warmup):
+    """Warm up, then time `steps` steps from the workload's u0.  Returns the
+    final field, wall seconds and the per-stage event timings."""
+    p = wl.problem.replace(precision=precision)
+    st = etd.Stepper(p)
+    u0 = wl.u0()
+    u = st.field(u0)
+    if warmup:
+        st.advance(u, warmup)
+    u = st.field(u0)
+    etd.etd_timing_enable(st.plan, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.advance(u, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, counts = etd.etd_timing_read(st.plan)
+    etd.etd_timing_enable(st.plan, False)
+    st.close()
+    return u, t1 - t0, ms, counts
+
+
+def roofline(wl, precision, ms, counts):
+    n = wl.problem.n[0]
+    per_product = 2.0 * n * n ** 3          # one dense mode product, true (unpadded) n
+    stages = {}
+    for k, name in enumerate(STAGE_NAMES):
+        if counts[k] == 0:
+            continue
+        avg_ms = ms[k] / counts[k]
+        flops = PRODUCTS[k] * per_product
+        stages[name] = {"launches": counts[k], "avg_ms": avg_ms, "tflops": flops / (avg_ms * 1e-3) / 1e12}
+    dom = max(stages, key=lambda s: stages[s]["avg_ms"] * stages[s]["launches"])
+    a = stages[dom]["tflops"]
+    peak = PEAK_TFLOPS[precision]
+    return {"bound": "mfma", "kernel": dom, "achieved": round(a, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(a / peak, 4), "traffic": None}, stages
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the stepper is a single-device path "
+              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2601_06849_amd as etd
+    import workloads as W
+
+    wl = W.fisher3d(precision=args.precision, n=args.n, nsteps=args.steps)
+    npts = wl.problem.npoints
+    u_main, sec, ms, counts = timed_run(etd, torch, wl, args.precision, args.steps, args.warmup)
+    value = npts * args.steps / sec
+    roof, stages = roofline(wl, args.precision, ms, counts)
+    useful = 26.0 * args.n ** 4 * args.steps  # 13 mode products per 3-D step
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": [args.n] * 3, "kappa": wl.problem.kappa[0], "q": wl.problem.q,
+                   "tau": wl.problem.tau, "reaction": "u(1-u)", "precision": args.precision,
+                   "init": "sine product + 8 Gaussian bumps (sigma 0.05), seed %d" % wl.seed},
+        "roofline": roof,
+        "stages": stages,
+        "useful_tflops": useful / sec / 1e12,
+    }
+
+    if args.reduced != "none" and args.precision == "fp64":
+        u_red, sec_r, ms_r, counts_r = timed_run(etd, torch, wl, args.reduced, args.steps, args.warmup)
+        diff = (u_red.double() - u_main).norm() / u_main.norm()
+        roof_r, _ = roofline(wl, args.reduced, ms_r, counts_r)
+        out["reduced"] = {"precision": args.reduced, "value": npts * args.steps / sec_r,
+                          "ms_per_step": 1e3 * sec_r / args.steps, "speedup_vs_fp64": sec / sec_r,
+                          "rel_l2_vs_fp64": float(diff), "roofline": roof_r}
+
+    if not args.no_cpu_baseline:
+        import oracle
+        p = wl.problem.replace(precision="fp64")
+        u0 = wl.u0()
+        cores = oracle.threads(0)
+        t0 = time.perf_counter()
+        oracle.advance(p, u0, args.cpu_steps, nthreads=0)
+        cs = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": npts * args.cpu_steps / cs, "unit": "grid-point updates/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{args.cpu_steps} steps of {wl.name} from the same u0 "
+                                         f"({cs:.1f} s, FP64 complex Thomas line solves)"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

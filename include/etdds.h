@@ -1,0 +1,143 @@
+/*
+ * etdds: Pade-based dimension-split ETD2RK time stepping (ETD2RK-DS) for
+ * u_t - kappa Lap(u) + q u = f(x, t, u) on a 2-D rectangle or 3-D box with
+ * homogeneous Dirichlet data (paper Sec. 1), in the Sylvester/spectral form
+ * of Sec. 3.3.2, on AMD Instinct MI355X (gfx950).
+ *
+ * One step (Sec. 3.1, 2-D and 3-D equations; Algorithms 1-2) applies, per
+ * direction d, the rational operators Q_l(tau A_d) of the P_{0,2} family
+ * (or, with pade = 4, the P_{0,4} family of Sec. 5) to the grid through the
+ * reusable eigendecomposition A_d = P_d D_d P_d^T: a dense mode-d product
+ * with P_d, a Hadamard scaling by the rational factor of tau*lambda, and the
+ * product with P_d back.  The reaction f is evaluated inside the stage
+ * kernels.  All arithmetic of a step runs in HIP kernels on the device.
+ *
+ * Conventions shared by every call:
+ *  - n[d] counts interior points; h_d = (hi[d]-lo[d])/(n[d]+1) (Sec. 2.1).
+ *  - A field is a contiguous device array ncomp x nz x ny x nx, x fastest
+ *    (the vectorisation order of Sec. 2.1), nz = 1 in 2-D.  Its element type
+ *    is double for ETD_FP64 and float for ETD_FP32 and ETD_BF16X6.
+ *  - Device memory belongs to the caller: the field and one workspace buffer
+ *    of etd_plan_workspace_bytes() bytes (256-byte aligned).  The library
+ *    allocates no device memory.  A plan owns host memory only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued asynchronously on it, in stream order.
+ *  - Every call returns an etd_status.  Argument errors are detected on the
+ *    host before anything is enqueued and leave all buffers untouched.  HIP
+ *    launch errors return ETD_EHIP.  etd_last_error() gives a thread-local
+ *    message for the most recent failure.
+ */
+#ifndef ETDDS_H
+#define ETDDS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ETD_OK = 0,
+    ETD_EINVAL = -1,        /* invalid argument */
+    ETD_EUNSUPPORTED = -2,  /* valid problem this build cannot run (size limits) */
+    ETD_EWORKSPACE = -3,    /* workspace missing, misaligned or too small */
+    ETD_EHIP = -4,          /* HIP runtime error */
+    ETD_ENONFINITE = -5     /* etd_compare found NaN or Inf in the field */
+} etd_status;
+
+typedef enum {
+    ETD_FP64 = 0,   /* FP64 state, FP64 MFMA mode products */
+    ETD_FP32 = 1,   /* FP32 state, FP32 MFMA mode products */
+    ETD_BF16X6 = 2  /* FP32 state; mode products as six BF16 MFMA terms
+                       (hi/mid/lo splits of both operands), FP32 accumulation */
+} etd_precision;
+
+typedef enum {
+    ETD_RXN_NONE = 0,        /* f = 0 */
+    ETD_RXN_LINEAR = 1,      /* f = c u                                  p0 = c */
+    ETD_RXN_FISHER = 2,      /* f = a u (1-u)                            p0 = a */
+    ETD_RXN_ALLEN_CAHN = 3,  /* f = u - u^3 */
+    ETD_RXN_AC_MMS = 4,      /* f = u(1-u^2) + psi(x,t), psi chosen so that
+                                e^{-lam t} prod_d sin(pi (x_d-lo_d)/L_d) solves
+                                the equation (Example 5.1); p0 = lam, p1 != 0
+                                uses the discrete Laplacian eigenvalue */
+    ETD_RXN_SATURATING = 5,  /* f = rho u/(1-u) (Example 5.2)           p0 = rho */
+    ETD_RXN_FHN_CUBIC = 6,   /* fu = u(1-u)(u-a) - v, fv = eps(u - g v)  p = a, eps, g */
+    ETD_RXN_FHN_CLASSIC = 7  /* fu = u - u^3/3 - v, fv = eps(u - alpha v)
+                                (Example 5.3)                            p = eps, alpha */
+} etd_reaction;
+
+typedef struct {
+    int dim;               /* 2 or 3 */
+    int n[3];              /* interior points in x, y, z (n[2] ignored in 2-D) */
+    double lo[3], hi[3];   /* box (hi > lo) */
+    int ncomp;             /* 1, or 2 for the FitzHugh-Nagumo reactions */
+    double kappa[2];       /* diffusivity per component, >= 0 */
+    double q;              /* potential >= 0, q/dim per direction (Sec. 2.1) */
+    double tau;            /* time step > 0; T = nsteps*tau (Sec. 2.2) */
+    int rxn;               /* etd_reaction */
+    double rxn_param[8];
+    int pade;              /* 2: P_{0,2} family (Sec. 3.1); 4: P_{0,4} family (Sec. 5) */
+    int precision;         /* etd_precision */
+} etd_problem;
+
+typedef struct etd_plan etd_plan;
+
+/* Build a plan on the host (Sec. 3.4, steps 1-2 of Algorithms 1-2): the
+ * closed-form eigenpairs of every A_d and the rational factors of tau*lambda,
+ * computed in FP64.  *out receives a new plan (free with etd_plan_destroy).
+ * ETD_EINVAL on a malformed problem; ETD_EUNSUPPORTED when a padded grid
+ * direction exceeds 256 points or the stage tiles exceed the on-chip limits. */
+etd_status etd_plan_create(const etd_problem* prob, etd_plan** out);
+
+/* Bytes of device workspace the plan needs: eigenvector tables, rational
+ * factors and the stage buffers (five padded fields) and reduction scratch. */
+etd_status etd_plan_workspace_bytes(const etd_plan* plan, size_t* bytes);
+
+/* Copy the plan's tables into the workspace (asynchronous on `stream`; the
+ * plan's host tables stay valid until destroy).  Must precede etd_advance
+ * with the same workspace.  ETD_EWORKSPACE if bytes is too small or the
+ * pointer is not 256-byte aligned. */
+etd_status etd_plan_upload(const etd_plan* plan, void* workspace_dev, size_t bytes, void* stream);
+
+/* Advance the field u_dev (device, layout above, updated in place) by nsteps
+ * steps from time t0 (the time argument of f).  nsteps = 0 is a no-op.
+ * Asynchronous on `stream`. */
+etd_status etd_advance(const etd_plan* plan, void* u_dev, double t0, int nsteps,
+                       void* workspace_dev, void* stream);
+
+/* Validation reductions over the interior (all components): out[0] =
+ * ||a - b||_2, out[1] = ||b||_2, out[2] = max |a - b|, out[3] = number of
+ * non-finite entries of a.  Accumulates in FP64 in a fixed order (repeatable).
+ * Synchronises `stream` to return the result.  Returns ETD_ENONFINITE (with
+ * out filled) when a holds NaN or Inf. */
+etd_status etd_compare(const etd_plan* plan, const void* a_dev, const void* b_dev, double out[4],
+                       void* workspace_dev, void* stream);
+
+/* Host copies of the plan's FP64 tables, for inspection and tests (no device
+ * involvement).  which: 0 = eigenvalues lambda_j of A_d (component comp),
+ * 1 = eigenvector matrix P_d (n_d x n_d, row-major), 2/3/4 = the rational
+ * factors Q_1, Q_2, Q_3 (or R_1..R_3) at tau*lambda_j.  count is the capacity
+ * of out in doubles; ETD_EINVAL if too small. */
+etd_status etd_plan_table(const etd_plan* plan, int which, int d, int comp, double* out, size_t count);
+
+/* Stage timing (diagnostics).  While enabled, etd_advance records a HIP event
+ * on its stream before and after every stage kernel.  etd_timing_read waits
+ * for the last recorded event and returns, per stage kind (0 = first outer
+ * stage: z in 3-D, y in 2-D, with f(t_n, U) fused; 1 = middle outer stage, y
+ * in 3-D; 2 = fused x stage), the summed milliseconds and the number of
+ * launches since the previous read or enable, then resets the counters.
+ * Enabling or disabling also resets them.  Not thread-safe per plan. */
+etd_status etd_timing_enable(etd_plan* plan, int enable);
+etd_status etd_timing_read(etd_plan* plan, double ms[3], long long counts[3]);
+
+/* Free the plan (host memory and any timing events). */
+etd_status etd_plan_destroy(etd_plan* plan);
+
+const char* etd_status_string(etd_status s);
+const char* etd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

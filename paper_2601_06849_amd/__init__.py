@@ -1,0 +1,233 @@
+"""Python binding of libetdds: the spectral ETD2RK-DS stepper for MI355X.
+
+Argument marshalling only.  Every step of the method runs in the HIP kernels
+of ``libetdds.so`` (built in-tree by ``paper_2601_06849_amd.build``); the
+functions below carry the same names as the C entry points declared in
+``include/etdds.h`` and take torch device tensors for the field and the
+workspace.  There is no fallback: if the library is missing or was built
+for another GPU, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libetdds.so")
+
+ETD_OK, ETD_EINVAL, ETD_EUNSUPPORTED, ETD_EWORKSPACE, ETD_EHIP, ETD_ENONFINITE = 0, -1, -2, -3, -4, -5
+ETD_FP64, ETD_FP32, ETD_BF16X6 = 0, 1, 2
+
+RXN = {"none": 0, "linear": 1, "fisher": 2, "allen_cahn": 3, "ac_mms": 4, "saturating": 5,
+       "fhn_cubic": 6, "fhn_classic": 7}
+PRECISION = {"fp64": ETD_FP64, "fp32": ETD_FP32, "bf16x6": ETD_BF16X6}
+
+
+class EtdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"etdds status {status}: {message}")
+        self.status = status
+
+
+class etd_problem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("ncomp", ctypes.c_int),
+        ("kappa", ctypes.c_double * 2),
+        ("q", ctypes.c_double),
+        ("tau", ctypes.c_double),
+        ("rxn", ctypes.c_int),
+        ("rxn_param", ctypes.c_double * 8),
+        ("pade", ctypes.c_int),
+        ("precision", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+EXPORTS = ("etd_plan_create", "etd_plan_workspace_bytes", "etd_plan_upload", "etd_advance", "etd_compare",
+           "etd_plan_table", "etd_timing_enable", "etd_timing_read", "etd_plan_destroy", "etd_status_string",
+           "etd_last_error")
+
+
+def lib():
+    """Load libetdds.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2601_06849_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, dp, ip = ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+        L.etd_plan_create.argtypes = [ctypes.POINTER(etd_problem), ctypes.POINTER(vp)]
+        L.etd_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.etd_plan_upload.argtypes = [vp, vp, sz, vp]
+        L.etd_advance.argtypes = [vp, vp, ctypes.c_double, ip, vp, vp]
+        L.etd_compare.argtypes = [vp, vp, vp, dp, vp, vp]
+        L.etd_plan_table.argtypes = [vp, ip, ip, ip, dp, sz]
+        L.etd_timing_enable.argtypes = [vp, ip]
+        L.etd_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
+        L.etd_plan_destroy.argtypes = [vp]
+        L.etd_status_string.argtypes = [ip]
+        L.etd_status_string.restype = ctypes.c_char_p
+        L.etd_last_error.argtypes = []
+        L.etd_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS[:9]:
+            getattr(L, name).restype = ip
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != ETD_OK:
+        raise EtdError(status, lib().etd_last_error().decode())
+
+
+def problem_struct(p) -> etd_problem:
+    """etd_problem from a workloads.Problem."""
+    s = etd_problem()
+    s.dim = p.dim
+    for d in range(3):
+        s.n[d] = p.n[d] if d < p.dim else 1
+        s.lo[d] = p.lo[d]
+        s.hi[d] = p.hi[d]
+    s.ncomp = p.ncomp
+    for c in range(p.ncomp):
+        s.kappa[c] = p.kappa[c]
+    s.q = p.q
+    s.tau = p.tau
+    s.rxn = RXN[p.reaction]
+    for i, v in enumerate(p.params):
+        s.rxn_param[i] = v
+    s.pade = p.pade
+    s.precision = PRECISION[p.precision]
+    return s
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------------------
+# entry points (same names as include/etdds.h)
+# --------------------------------------------------------------------------
+
+def etd_plan_create(problem) -> ctypes.c_void_p:
+    s = problem if isinstance(problem, etd_problem) else problem_struct(problem)
+    h = ctypes.c_void_p()
+    _check(lib().etd_plan_create(ctypes.byref(s), ctypes.byref(h)))
+    return h
+
+
+def etd_plan_workspace_bytes(plan) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().etd_plan_workspace_bytes(plan, ctypes.byref(n)))
+    return int(n.value)
+
+
+def etd_plan_upload(plan, workspace, stream=None):
+    _check(lib().etd_plan_upload(plan, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                 _stream(stream)))
+
+
+def etd_advance(plan, u, t0: float, nsteps: int, workspace, stream=None):
+    if not u.is_contiguous():
+        raise ValueError("field must be contiguous")
+    _check(lib().etd_advance(plan, _ptr(u), float(t0), int(nsteps), _ptr(workspace), _stream(stream)))
+
+
+def etd_compare(plan, a, b, workspace, stream=None, allow_nonfinite: bool = False):
+    out = (ctypes.c_double * 4)()
+    st = lib().etd_compare(plan, _ptr(a), _ptr(b), out, _ptr(workspace), _stream(stream))
+    if not (allow_nonfinite and st == ETD_ENONFINITE):
+        _check(st)
+    return tuple(out)
+
+
+def etd_plan_table(plan, which: int, d: int, comp: int, count: int) -> np.ndarray:
+    out = np.zeros(count, dtype=np.float64)
+    _check(lib().etd_plan_table(plan, which, d, comp, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                count))
+    return out
+
+
+def etd_timing_enable(plan, enable: bool = True):
+    _check(lib().etd_timing_enable(plan, int(bool(enable))))
+
+
+def etd_timing_read(plan):
+    """(ms[3], counts[3]) per stage kind: 0 first outer, 1 middle outer, 2 x stage."""
+    ms = (ctypes.c_double * 3)()
+    cnt = (ctypes.c_longlong * 3)()
+    _check(lib().etd_timing_read(plan, ms, cnt))
+    return list(ms), list(cnt)
+
+
+def etd_plan_destroy(plan):
+    _check(lib().etd_plan_destroy(plan))
+
+
+def etd_status_string(status: int) -> str:
+    return lib().etd_status_string(status).decode()
+
+
+def etd_last_error() -> str:
+    return lib().etd_last_error().decode()
+
+
+# --------------------------------------------------------------------------
+# convenience: plan + workspace owned together
+# --------------------------------------------------------------------------
+
+class Stepper:
+    """A plan with its torch-allocated workspace on one device."""
+
+    def __init__(self, problem, device="cuda:0", stream=None):
+        import torch
+        self.problem = problem
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if problem.precision == "fp64" else torch.float32
+        self.plan = etd_plan_create(problem)
+        nbytes = etd_plan_workspace_bytes(self.plan)
+        # over-allocate so the workspace can start on a 256-byte boundary
+        self._raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._raw.data_ptr()) % 256
+        self.workspace = self._raw[off:off + nbytes]
+        self.stream = stream
+        etd_plan_upload(self.plan, self.workspace, self.stream)
+
+    def field(self, u0: np.ndarray):
+        import torch
+        return torch.as_tensor(np.ascontiguousarray(u0), dtype=self.dtype).reshape(self.problem.shape).to(
+            self.device).contiguous()
+
+    def advance(self, u, nsteps: int, t0: float = 0.0):
+        etd_advance(self.plan, u, t0, nsteps, self.workspace, self.stream)
+        return u
+
+    def compare(self, a, b, allow_nonfinite=False):
+        return etd_compare(self.plan, a, b, self.workspace, self.stream, allow_nonfinite)
+
+    def close(self):
+        if self.plan is not None:
+            etd_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,251 @@
+// Plan construction for the spectral ETD2RK-DS stepper (host, FP64).
+//
+// Steps 1-2 of Algorithms 1-2 (Sec. 3.4): the eigendecomposition of every
+// 1-D operator and the Hadamard factors of the rational functions.  The
+// matrices of Sec. 2.1, A_d = h_d^-2 tridiag(-kappa, 2 kappa + q h_d^2/dim,
+// -kappa), are the scaled second-difference matrix plus a multiple of I, so
+// their eigenvectors are the discrete sine vectors and the eigendecomposition
+// is taken in closed form:
+//   P_d[i][j] = sqrt(2/(n+1)) sin(pi (i+1)(j+1)/(n+1))   (symmetric, P_d^2 = I)
+//   lambda_j  = kappa (4/h^2) sin^2((j+1) pi / (2(n+1))) + q/dim.
+// Only the operator P diag(.) P^T is unique; this choice of P (sign, order)
+// makes it symmetric and orthogonal, so the forward and backward products use
+// the same matrix.
+//
+// The complex partial fractions of Sec. 3.1 are needed only to form the
+// Hadamard factors (Remark 1): 2 Re(r_l/(z - s)) equals the real rational
+// function, evaluated here directly.  The stepper uses the increment form
+// Q(z) = Q(0) + (Q(z) - Q(0)), so the factors are stored as Q1 - 1,
+// tau (Q2 - 1) and Q3 - 1/2, each written with a factor z taken out so that
+// no cancellation occurs as tau*lambda -> 0.
+#include "plan.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+namespace etdds {
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Rational factors at z = tau*lambda >= 0.  out[0..2] = Q_1..Q_3 and
+// inc[0..2] = Q_1 - 1, Q_2 - 1, Q_3 - 1/2.
+void rational(int pade, double z, double out[3], double inc[3]) {
+    if (pade == 4) {
+        // P_{0,4} family (Sec. 5): R_1 = 24/den, R_2 = (z^3+4z^2+12z+24)/den,
+        // R_3 = (z^3+3z^2+8z+12)/den, den = z^4+4z^3+12z^2+24z+24.
+        const double den = (((z + 4.0) * z + 12.0) * z + 24.0) * z + 24.0;
+        const double n2 = ((z + 4.0) * z + 12.0) * z + 24.0;
+        const double n3 = ((z + 3.0) * z + 8.0) * z + 12.0;
+        out[0] = 24.0 / den;
+        out[1] = n2 / den;
+        out[2] = n3 / den;
+        inc[0] = -z * n2 / den;
+        inc[1] = -z * n3 / den;
+        inc[2] = -z * (((z + 2.0) * z + 6.0) * z + 8.0) / (2.0 * den);
+    } else {
+        // P_{0,2} family (Sec. 3.1): Q_1 = 2/D, Q_2 = (z+2)/D, Q_3 = (z+1)/D,
+        // D = z^2 + 2z + 2.
+        const double D = (z + 2.0) * z + 2.0;
+        out[0] = 2.0 / D;
+        out[1] = (z + 2.0) / D;
+        out[2] = (z + 1.0) / D;
+        inc[0] = -z * (z + 2.0) / D;
+        inc[1] = -z * (z + 1.0) / D;
+        inc[2] = -z * z / (2.0 * D);
+    }
+}
+
+// Round-to-nearest-even conversion to bfloat16 (upper 16 bits of binary32).
+uint16_t to_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return uint16_t(u >> 16);
+}
+
+double from_bf16(uint16_t h) {
+    const uint32_t u = uint32_t(h) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return double(f);
+}
+
+template <typename T>
+void put(std::vector<uint8_t>& img, size_t off, size_t idx, T v) {
+    std::memcpy(img.data() + off + idx * sizeof(T), &v, sizeof(T));
+}
+
+}  // namespace
+
+etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
+    std::ostringstream msg;
+    auto bad = [&](const char* what) {
+        err = what;
+        return ETD_EINVAL;
+    };
+    if (p.dim != 2 && p.dim != 3) return bad("dim must be 2 or 3");
+    if (p.ncomp != 1 && p.ncomp != 2) return bad("ncomp must be 1 or 2");
+    const bool two = p.rxn == ETD_RXN_FHN_CUBIC || p.rxn == ETD_RXN_FHN_CLASSIC;
+    if (p.rxn < ETD_RXN_NONE || p.rxn > ETD_RXN_FHN_CLASSIC) return bad("unknown reaction");
+    if (two != (p.ncomp == 2)) return bad("ncomp must be 2 exactly for the FitzHugh-Nagumo reactions");
+    if (p.pade != 2 && p.pade != 4) return bad("pade must be 2 or 4");
+    if (p.precision < ETD_FP64 || p.precision > ETD_BF16X6) return bad("unknown precision");
+    if (!(p.tau > 0.0) || !std::isfinite(p.tau)) return bad("tau must be a finite positive number");
+    if (!(p.q >= 0.0) || !std::isfinite(p.q)) return bad("q must be finite and >= 0");
+    for (int c = 0; c < p.ncomp; ++c)
+        if (!(p.kappa[c] >= 0.0) || !std::isfinite(p.kappa[c])) return bad("kappa must be finite and >= 0");
+    for (int i = 0; i < 8; ++i)
+        if (!std::isfinite(p.rxn_param[i])) return bad("reaction parameters must be finite");
+    for (int d = 0; d < p.dim; ++d) {
+        if (p.n[d] < 1) return bad("n must be >= 1 in every direction");
+        if (!(p.hi[d] > p.lo[d]) || !std::isfinite(p.hi[d] - p.lo[d])) return bad("box must have hi > lo");
+    }
+
+    pl.prob = p;
+    pl.dim = p.dim;
+    pl.nc = p.ncomp;
+    for (int d = 0; d < 3; ++d) {
+        pl.n[d] = d < p.dim ? p.n[d] : 1;
+        pl.np[d] = d < p.dim ? round_up(pl.n[d], kPad) : 1;
+    }
+    for (int d = 0; d < p.dim; ++d)
+        if (pl.np[d] > kMaxPadded) {
+            msg << "padded direction " << d << " has " << pl.np[d] << " points; the fused stage kernels take at most "
+                << kMaxPadded;
+            err = msg.str();
+            return ETD_EUNSUPPORTED;
+        }
+    pl.elem = p.precision == ETD_FP64 ? 8 : 4;
+    for (int d = 0; d < p.dim; ++d) {
+        const int NP = pl.np[d];
+        const size_t outer = size_t(2 * pl.nc) * NP * (16 + kOuterRowPad) * pl.elem;
+        const size_t inner = size_t(2 * pl.nc) * 16 * (NP + kInnerRowPad) * pl.elem;
+        if (outer > kMaxLds || inner > kMaxLds) {
+            err = "stage tile exceeds the LDS budget for this size, precision and component count";
+            return ETD_EUNSUPPORTED;
+        }
+    }
+
+    // ---- FP64 tables -------------------------------------------------------
+    for (int d = 0; d < p.dim; ++d) {
+        const int n = pl.n[d];
+        const double h = (p.hi[d] - p.lo[d]) / (n + 1);
+        pl.P[d].assign(size_t(n) * n, 0.0);
+        const double s = std::sqrt(2.0 / (n + 1));
+        const long period = 2L * (n + 1);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const long arg = (long(i + 1) * long(j + 1)) % period;  // exact argument reduction
+                pl.P[d][size_t(i) * n + j] = s * std::sin(M_PI * double(arg) / double(n + 1));
+            }
+        for (int c = 0; c < pl.nc; ++c) {
+            pl.lam[d][c].resize(n);
+            for (int l = 0; l < 3; ++l) pl.rat[d][c][l].resize(n);
+            for (int j = 0; j < n; ++j) {
+                const double sn = std::sin((j + 1) * M_PI / (2.0 * (n + 1)));
+                const double lam = p.kappa[c] * 4.0 / (h * h) * sn * sn + p.q / p.dim;
+                pl.lam[d][c][j] = lam;
+                double q[3], inc[3];
+                rational(p.pade, p.tau * lam, q, inc);
+                for (int l = 0; l < 3; ++l) pl.rat[d][c][l][j] = q[l];
+            }
+        }
+    }
+
+    // ---- workspace layout ----------------------------------------------------
+    Layout& L = pl.lay;
+    size_t off = 0;
+    const bool bf = p.precision == ETD_BF16X6;
+    for (int d = 0; d < 3; ++d) {
+        if (d < p.dim) {
+            const size_t nn = size_t(pl.np[d]) * pl.np[d];
+            L.P[d] = off;
+            L.P_bytes[d] = bf ? 3 * nn * 2 : nn * pl.elem;
+            off = align256(off + L.P_bytes[d]);
+        } else {
+            L.P[d] = 0;
+            L.P_bytes[d] = 0;
+        }
+    }
+    pl.diag_stride = size_t(kMaxPadded);
+    const size_t diag_elem = bf ? 4 : pl.elem;
+    L.diag = off;
+    L.diag_bytes = size_t(pl.nc) * kDiagSlots * pl.diag_stride * diag_elem;
+    off = align256(off + L.diag_bytes);
+    L.sines = off;
+    off = align256(off + 3 * size_t(kMaxPadded) * 8);
+    pl.table_bytes = off;
+    L.field_bytes = align256(size_t(pl.nc) * pl.np[0] * pl.np[1] * pl.np[2] * pl.elem);
+    for (int f = 0; f < 5; ++f) {
+        L.field[f] = off;
+        off += L.field_bytes;
+    }
+    L.reduce = off;
+    off = align256(off + 2048 * 4 * 8);
+    L.total = off;
+
+    // ---- host image of the tables -------------------------------------------
+    pl.image.assign(pl.table_bytes, 0);
+    for (int d = 0; d < p.dim; ++d) {
+        const int n = pl.n[d], NP = pl.np[d];
+        const size_t nn = size_t(NP) * NP;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double v = pl.P[d][size_t(i) * n + j];
+                const size_t idx = size_t(i) * NP + j;
+                if (p.precision == ETD_FP64) {
+                    put<double>(pl.image, L.P[d], idx, v);
+                } else if (p.precision == ETD_FP32) {
+                    put<float>(pl.image, L.P[d], idx, float(v));
+                } else {
+                    const uint16_t hi = to_bf16(float(v));
+                    const double r1 = v - from_bf16(hi);
+                    const uint16_t mid = to_bf16(float(r1));
+                    const double r2 = r1 - from_bf16(mid);
+                    const uint16_t lo = to_bf16(float(r2));
+                    put<uint16_t>(pl.image, L.P[d], idx, hi);
+                    put<uint16_t>(pl.image, L.P[d], nn + idx, mid);
+                    put<uint16_t>(pl.image, L.P[d], 2 * nn + idx, lo);
+                }
+            }
+    }
+    // Diagonal slots: outer directions (z, y) use Q1 - 1; x uses all three.
+    for (int c = 0; c < pl.nc; ++c) {
+        for (int slot = 0; slot < kDiagSlots; ++slot) {
+            int d;
+            if (slot == kDiagZ) d = 2;
+            else if (slot == kDiagY) d = 1;
+            else d = 0;
+            if (d >= p.dim) continue;
+            for (int j = 0; j < pl.n[d]; ++j) {
+                double q[3], inc[3];
+                rational(p.pade, p.tau * pl.lam[d][c][j], q, inc);
+                double v;
+                if (slot == kDiagZ || slot == kDiagY || slot == kDiagX1) v = inc[0];
+                else if (slot == kDiagX2) v = p.tau * inc[1];
+                else v = inc[2];
+                const size_t idx = (size_t(c) * kDiagSlots + slot) * pl.diag_stride + j;
+                if (p.precision == ETD_FP64) put<double>(pl.image, L.diag, idx, v);
+                else put<float>(pl.image, L.diag, idx, float(v));
+            }
+        }
+    }
+    // Sine factors of the manufactured solution (zero on the padding).
+    for (int d = 0; d < p.dim; ++d) {
+        const double Ld = p.hi[d] - p.lo[d];
+        const double h = Ld / (pl.n[d] + 1);
+        for (int i = 0; i < pl.n[d]; ++i)
+            put<double>(pl.image, L.sines, size_t(d) * kMaxPadded + i, std::sin(M_PI * (i + 1) * h / Ld));
+    }
+    if (p.dim == 2)
+        for (int i = 0; i < kMaxPadded; ++i) put<double>(pl.image, L.sines, 2 * size_t(kMaxPadded) + i, i == 0 ? 1.0 : 0.0);
+    return ETD_OK;
+}
+
+}  // namespace etdds

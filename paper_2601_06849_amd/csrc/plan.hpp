@@ -1,0 +1,66 @@
+// Host-side plan of the spectral ETD2RK-DS stepper: closed-form eigenpairs of
+// the 1-D operators, rational factors in FP64, and the workspace layout.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "etdds.h"
+
+namespace etdds {
+
+// Granularity of the padded grid: every direction is padded with zeros to a
+// multiple of 32 (one BF16 MFMA K-step; two FP64/FP32 16-row tiles).
+constexpr int kPad = 32;
+// Largest padded direction the fused stage kernels support.
+constexpr int kMaxPadded = 256;
+// LDS budget of one stage workgroup (bytes).
+constexpr size_t kMaxLds = 160 * 1024;
+
+// Row strides (in elements) of the LDS tiles, padded against bank conflicts.
+constexpr int kOuterRowPad = 0;
+constexpr int kInnerRowPad = 4;
+
+struct Layout {
+    size_t P[3];        // eigenvector matrices (NP x NP, row-major; BF16X6: hi, mid, lo)
+    size_t P_bytes[3];
+    size_t diag;        // increment-form rational factors, see DiagSlot
+    size_t diag_bytes;
+    size_t sines;       // FP64 sin(pi (x_i - lo)/L) per direction (AC_MMS forcing)
+    size_t field[5];    // padded fields: U, WA, WB, WC, WD
+    size_t field_bytes;
+    size_t reduce;      // FP64 partial sums of etd_compare
+    size_t total;
+};
+
+// Slots of the per-component diagonal table (each NP[d] long, working type).
+enum DiagSlot {
+    kDiagZ = 0,   // Q1(tau lambda_z) - 1
+    kDiagY = 1,   // Q1(tau lambda_y) - 1
+    kDiagX1 = 2,  // Q1(tau lambda_x) - 1
+    kDiagX2 = 3,  // tau (Q2(tau lambda_x) - 1)
+    kDiagX3 = 4,  // Q3(tau lambda_x) - 1/2
+    kDiagSlots = 5
+};
+
+struct Plan {
+    etd_problem prob;
+    int dim = 0, nc = 0;
+    int n[3] = {1, 1, 1};
+    int np[3] = {1, 1, 1};
+    size_t elem = 8;                        // bytes per state element
+    // FP64 host tables
+    std::vector<double> lam[3][2];          // eigenvalues of A_d (kappa_c applied)
+    std::vector<double> P[3];               // n_d x n_d eigenvector matrix
+    std::vector<double> rat[3][2][3];       // Q_l(tau lambda_j), l = 1..3
+    Layout lay{};
+    std::vector<uint8_t> image;             // host image of the table region
+    size_t table_bytes = 0;                 // bytes of image (start of workspace)
+    size_t diag_stride = 0;                 // elements between diag slots (max NP)
+};
+
+etd_status build_plan(const etd_problem& p, Plan& out, std::string& err);
+
+}  // namespace etdds

@@ -1,0 +1,169 @@
+"""Host-side checks of the C ABI: the library loads and exports every entry
+point the header declares; plan construction (host FP64, no GPU) builds the
+closed-form eigenpairs and the rational factors of Sec. 3.3.2 / Sec. 3.1
+correctly; malformed arguments are rejected on the host before any device
+work."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def etd():
+    import paper_2601_06849_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_2601_06849_amd import build
+        build.build()
+    m.lib()
+    return m
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "etdds.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(etd_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(etd):
+    names = declared_functions()
+    assert len(names) >= 9
+    L = ctypes.CDLL(etd.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(etd.EXPORTS)
+
+
+def dense_stencil(p, d, c=0):
+    n, h, k = p.n[d], p.h(d), p.kappa[c]
+    A = np.diag(np.full(n, (2 * k + p.q * h * h / p.dim) / h ** 2))
+    A += np.diag(np.full(n - 1, -k / h ** 2), 1) + np.diag(np.full(n - 1, -k / h ** 2), -1)
+    return A
+
+
+def q_poly(pade, ell, x):
+    if pade == 2:
+        den = x * x + 2 * x + 2
+        return {1: 2 / den, 2: (x + 2) / den, 3: (x + 1) / den}[ell]
+    den = x ** 4 + 4 * x ** 3 + 12 * x ** 2 + 24 * x + 24
+    return {1: 24 / den, 2: (x ** 3 + 4 * x ** 2 + 12 * x + 24) / den, 3: (x ** 3 + 3 * x ** 2 + 8 * x + 12) / den}[ell]
+
+
+@pytest.mark.parametrize("pade", [2, 4])
+def test_plan_tables_match_dense_eigendecomposition(etd, pade):
+    p = W.Problem(dim=3, n=(17, 40, 9), kappa=(0.3, 2.0), q=0.9, tau=0.02, reaction="fhn_cubic", pade=pade,
+                  lo=(0.0, -1.0, 0.5), hi=(2.0, 1.5, 1.0))
+    plan = etd.etd_plan_create(p)
+    try:
+        for d in range(3):
+            n = p.n[d]
+            P = etd.etd_plan_table(plan, 1, d, 0, n * n).reshape(n, n)
+            assert np.abs(P @ P.T - np.eye(n)).max() < 1e-14 * n
+            assert np.abs(P - P.T).max() == 0.0
+            for c in range(2):
+                A = dense_stencil(p, d, c)
+                lam = etd.etd_plan_table(plan, 0, d, c, n)
+                # A P = P diag(lam) and the spectrum equals the dense one
+                assert np.abs(A @ P - P * lam).max() < 1e-12 * np.abs(A).max()
+                assert np.allclose(np.sort(lam), np.linalg.eigvalsh(A), rtol=1e-12, atol=1e-12)
+                for ell in (1, 2, 3):
+                    qv = etd.etd_plan_table(plan, 1 + ell, d, c, n)
+                    assert np.allclose(qv, q_poly(pade, ell, p.tau * lam), rtol=1e-14, atol=0)
+                    # the operator P diag(q) P^T equals Q_ell(tau A) from its polynomial definition
+                    M = p.tau * A
+                    I = np.eye(n)
+                    if pade == 2:
+                        den = M @ M + 2 * M + 2 * I
+                        num = {1: 2 * I, 2: M + 2 * I, 3: M + I}[ell]
+                    else:
+                        M2 = M @ M
+                        den = M2 @ M2 + 4 * M2 @ M + 12 * M2 + 24 * M + 24 * I
+                        num = {1: 24 * I, 2: M2 @ M + 4 * M2 + 12 * M + 24 * I,
+                               3: M2 @ M + 3 * M2 + 8 * M + 12 * I}[ell]
+                    assert np.abs((P * qv) @ P.T - np.linalg.solve(den, num)).max() < 1e-12
+    finally:
+        etd.etd_plan_destroy(plan)
+
+
+def test_rational_factors_bounded(etd):
+    """0 < Q1 <= 1, 0 < Q2 <= 1, 0 < Q3 <= 1/2 at tau*lambda >= 0 (Prop. 4.3)."""
+    p = W.Problem(dim=2, n=(200, 3), kappa=(5.0,), q=0.2, tau=0.5, reaction="fisher")
+    plan = etd.etd_plan_create(p)
+    try:
+        q1, q2, q3 = (etd.etd_plan_table(plan, w, 0, 0, 200) for w in (2, 3, 4))
+        assert np.all((q1 > 0) & (q1 <= 1)) and np.all((q2 > 0) & (q2 <= 1)) and np.all((q3 > 0) & (q3 <= 0.5))
+    finally:
+        etd.etd_plan_destroy(plan)
+
+
+BAD = [
+    dict(dim=4),
+    dict(ncomp=3),
+    dict(tau=0.0),
+    dict(tau=float("nan")),
+    dict(kappa0=-1.0),
+    dict(q=-0.5),
+    dict(n0=0),
+    dict(pade=3),
+    dict(precision=7),
+    dict(rxn=42),
+    dict(rxn=6),          # FitzHugh-Nagumo with one component
+    dict(hi0=0.0),        # empty box
+]
+
+
+@pytest.mark.parametrize("mod", BAD, ids=lambda m: ",".join(m))
+def test_plan_rejects_malformed_problem(etd, mod):
+    s = etd.problem_struct(W.Problem(dim=2, n=(10, 12), kappa=(0.1,), tau=0.01, reaction="fisher"))
+    for k, v in mod.items():
+        if k == "kappa0":
+            s.kappa[0] = v
+        elif k == "n0":
+            s.n[0] = v
+        elif k == "hi0":
+            s.hi[0] = v
+        else:
+            setattr(s, k, v)
+    with pytest.raises(etd.EtdError) as ei:
+        etd.etd_plan_create(s)
+    assert ei.value.status == etd.ETD_EINVAL
+
+
+def test_plan_reports_unsupported_sizes(etd):
+    p = W.Problem(dim=2, n=(300, 10), kappa=(0.1,), tau=0.01, reaction="fisher")
+    with pytest.raises(etd.EtdError) as ei:
+        etd.etd_plan_create(p)
+    assert ei.value.status == etd.ETD_EUNSUPPORTED
+
+
+def test_host_side_argument_errors_touch_nothing(etd):
+    """Workspace and step-count errors are caught before any HIP call, so fake
+    device addresses are never dereferenced."""
+    L = etd.lib()
+    p = W.Problem(dim=2, n=(31, 31), kappa=(0.1,), tau=0.01, reaction="fisher")
+    plan = etd.etd_plan_create(p)
+    try:
+        nbytes = etd.etd_plan_workspace_bytes(plan)
+        assert nbytes > 0 and nbytes % 256 == 0
+        fake_u = ctypes.c_void_p(0x1000)
+        misaligned = ctypes.c_void_p(0x1008)
+        assert L.etd_advance(plan, fake_u, 0.0, 1, misaligned, None) == etd.ETD_EWORKSPACE
+        assert L.etd_advance(plan, fake_u, 0.0, 1, None, None) == etd.ETD_EWORKSPACE
+        assert L.etd_advance(plan, fake_u, 0.0, -1, ctypes.c_void_p(0x10000), None) == etd.ETD_EINVAL
+        assert L.etd_advance(plan, None, 0.0, 1, ctypes.c_void_p(0x10000), None) == etd.ETD_EINVAL
+        assert L.etd_advance(plan, fake_u, float("inf"), 1, ctypes.c_void_p(0x10000), None) == etd.ETD_EINVAL
+        assert L.etd_advance(None, fake_u, 0.0, 1, ctypes.c_void_p(0x10000), None) == etd.ETD_EINVAL
+        # nsteps = 0 is a no-op that returns before touching the device
+        assert L.etd_advance(plan, fake_u, 0.0, 0, ctypes.c_void_p(0x10000), None) == etd.ETD_OK
+        assert L.etd_plan_upload(plan, ctypes.c_void_p(0x10000), nbytes - 1, None) == etd.ETD_EWORKSPACE
+        assert "smaller" in etd.etd_last_error()
+        assert etd.etd_status_string(etd.ETD_EWORKSPACE) == "bad workspace"
+    finally:
+        etd.etd_plan_destroy(plan)

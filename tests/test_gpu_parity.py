@@ -1,0 +1,236 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bar: relative L2 error <= 1e-12 in FP64 (both sides apply the same split
+Pade operators; the paper prints identical errors for its two solvers,
+Sec. 5), and <= 1e-6 for the reduced-precision mode products against the
+FP64 oracle.  Inputs are seeded and synthetic (module ``workloads``).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+REDUCED_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def etd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2601_06849_amd as m
+    m.lib()
+    return m
+
+
+def run_gpu(etd, p, u0, nsteps, t0=0.0):
+    import torch
+    st = etd.Stepper(p)
+    u = st.field(u0)
+    st.advance(u, nsteps, t0)
+    torch.cuda.synchronize()
+    out = u.cpu().numpy().astype(np.float64)
+    st.close()
+    return out
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def check(etd, oracle_mod, p, u0, nsteps, tol=FP64_TOL, t0=0.0):
+    ref = oracle_mod.advance(p, u0, nsteps, t0=t0)
+    got = run_gpu(etd, p, u0, nsteps, t0)
+    err = rel_l2(got, ref)
+    print(f"  rel_l2={err:.3e} max_abs={np.abs(got - ref).max():.3e}")
+    assert np.all(np.isfinite(got))
+    assert err <= tol, err
+    return got, ref
+
+
+# ---------------------------------------------------------------------------
+# the named workloads
+# ---------------------------------------------------------------------------
+
+def test_fisher2d_n63_full_run(etd, oracle_mod):
+    """2-D Fisher-KPP, 63^2, 100 steps, FP64 (the small workload, whole run)."""
+    wl = W.fisher2d_small()
+    check(etd, oracle_mod, wl.problem, wl.u0(), wl.nsteps)
+
+
+def test_fisher3d_n255_full_size_steps(etd, oracle_mod):
+    """3-D Fisher-KPP at the benchmark size (255^3, 16.6M unknowns), FP64, in the
+    launch configuration the benchmark times; three steps against the oracle."""
+    wl = W.fisher3d()
+    check(etd, oracle_mod, wl.problem, wl.u0(), 3)
+
+
+def test_fisher3d_small_long_run(etd, oracle_mod):
+    wl = W.fisher3d(n=47, nsteps=200)
+    check(etd, oracle_mod, wl.problem, wl.u0(), wl.nsteps)
+
+
+# ---------------------------------------------------------------------------
+# sizes: ragged tails, tiny and maximum extents
+# ---------------------------------------------------------------------------
+
+SIZES = [
+    (2, (37, 50)), (2, (1, 64)), (2, (96, 3)), (2, (256, 256)), (2, (255, 17)),
+    (3, (20, 45, 33)), (3, (1, 1, 1)), (3, (64, 7, 130)), (3, (33, 32, 31)),
+]
+
+
+@pytest.mark.parametrize("dim,n", SIZES, ids=lambda v: str(v))
+def test_sizes_fp64(etd, oracle_mod, dim, n):
+    p = W.Problem(dim=dim, n=n, kappa=(0.7,), q=0.35, tau=0.004, reaction="fisher", rxn_param=(1.4,),
+                  lo=(0.1, -0.5, 1.0), hi=(1.3, 0.7, 1.6))
+    u0 = W.u0_random(p, seed=5, lo=0.0, hi=1.0)
+    check(etd, oracle_mod, p, u0, 7)
+
+
+def test_max_extent_3d(etd, oracle_mod):
+    """Every direction at the largest supported padded extent (256, no padding)."""
+    p = W.Problem(dim=3, n=(256, 256, 256), kappa=(0.005,), q=0.5, tau=0.005, reaction="fisher")
+    u0 = W.u0_sine_bumps(p, seed=9)
+    check(etd, oracle_mod, p, u0, 2)
+
+
+# ---------------------------------------------------------------------------
+# reactions, rational families, components
+# ---------------------------------------------------------------------------
+
+RXNS = [
+    ("none", (), (0.3,)), ("linear", (-1.7,), (0.3,)), ("fisher", (1.0,), (0.02,)),
+    ("allen_cahn", (), (0.5,)), ("ac_mms", (1.0, 0.0), (1.0,)), ("ac_mms", (2.0, 1.0), (0.4,)),
+    ("saturating", (0.1,), (1.0,)), ("fhn_cubic", (0.1, 0.01, 0.5), (1e-2, 1e-3)),
+    ("fhn_classic", (1.0, 1.0), (0.01, 10.0)),
+]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("rxn,params,kappa", RXNS, ids=lambda v: str(v))
+def test_reactions_fp64(etd, oracle_mod, dim, rxn, params, kappa):
+    n = (70, 41) if dim == 2 else (24, 40, 19)
+    p = W.Problem(dim=dim, n=n, kappa=kappa, q=0.2, tau=0.01, reaction=rxn, rxn_param=params)
+    if rxn.startswith("fhn"):
+        u0 = W.u0_fhn_patch(p, seed=3, patch=0.3)
+    else:
+        u0 = 0.9 * W.sine_product(p)[None] + 0.05 * W.u0_random(p, seed=4, lo=0, hi=1)
+    check(etd, oracle_mod, p, u0, 12, t0=0.25)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_pade04_family(etd, oracle_mod, dim):
+    n = (63, 52) if dim == 2 else (31, 28, 35)
+    p = W.Problem(dim=dim, n=n, kappa=(1.0,), q=0.0, tau=1 / 32, reaction="ac_mms", rxn_param=(1.0, 0.0), pade=4)
+    check(etd, oracle_mod, p, W.sine_product(p)[None], 16)
+
+
+def test_heun_degenerate_case(etd, oracle_mod):
+    """kappa = q = 0: the step reduces to Heun's method pointwise."""
+    p = W.Problem(dim=3, n=(30, 20, 10), kappa=(0.0,), q=0.0, tau=0.1, reaction="fisher")
+    u0 = W.u0_random(p, seed=2, lo=0, hi=1)
+    got, _ = check(etd, oracle_mod, p, u0, 1)
+    f0 = u0 * (1 - u0)
+    w = u0 + p.tau * f0
+    heun = w + 0.5 * p.tau * (w * (1 - w) - f0)
+    assert np.abs(got - heun).max() < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# reduced precision (FP32 state and FP32 MFMA products), error vs FP64 oracle
+# ---------------------------------------------------------------------------
+
+def test_fp32_fisher3d_against_fp64_oracle(etd, oracle_mod):
+    wl = W.fisher3d(n=63, nsteps=200)
+    p64 = wl.problem
+    ref = oracle_mod.advance(p64, wl.u0(), wl.nsteps)
+    got = run_gpu(etd, p64.replace(precision="fp32"), wl.u0(), wl.nsteps)
+    err = rel_l2(got, ref)
+    print(f"  fp32 rel_l2 vs fp64 oracle = {err:.3e}")
+    assert err <= REDUCED_TOL
+
+
+def test_fp32_fhn2d_against_fp64_oracle(etd, oracle_mod):
+    p = W.Problem(dim=2, n=(255, 255), kappa=(1e-4, 1e-5), q=0.0, tau=0.05, reaction="fhn_cubic",
+                  rxn_param=(0.1, 0.01, 0.5))
+    u0 = W.u0_fhn_patch(p, seed=W.SEED0 + 1)
+    ref = oracle_mod.advance(p, u0, 200)
+    got = run_gpu(etd, p.replace(precision="fp32"), u0, 200)
+    err = rel_l2(got, ref)
+    print(f"  fp32 rel_l2 vs fp64 oracle = {err:.3e}")
+    assert err <= REDUCED_TOL
+
+
+# ---------------------------------------------------------------------------
+# repeatability, resume, no-op, validation reductions
+# ---------------------------------------------------------------------------
+
+def test_bitwise_repeatable_and_resumable(etd):
+    import torch
+    wl = W.fisher3d(n=40)
+    st = etd.Stepper(wl.problem)
+    a = st.field(wl.u0())
+    b = st.field(wl.u0())
+    st.advance(a, 10)
+    st.advance(b, 5)
+    st.advance(b, 5, t0=5 * wl.problem.tau)
+    c = st.field(wl.u0())
+    st.advance(c, 10)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)
+    st.close()
+
+
+def test_zero_steps_is_noop(etd):
+    import torch
+    wl = W.fisher2d_small()
+    st = etd.Stepper(wl.problem)
+    u = st.field(wl.u0())
+    before = u.clone()
+    st.advance(u, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(u, before)
+    st.close()
+
+
+def test_compare_reduction(etd):
+    import torch
+    p = W.Problem(dim=3, n=(50, 31, 20), kappa=(0.1,), tau=0.01, reaction="fisher")
+    st = etd.Stepper(p)
+    rng = np.random.default_rng(0)
+    a = rng.normal(size=p.shape)
+    b = rng.normal(size=p.shape)
+    out = st.compare(st.field(a), st.field(b))
+    assert math.isclose(out[0], np.linalg.norm((a - b).ravel()), rel_tol=1e-12)
+    assert math.isclose(out[1], np.linalg.norm(b.ravel()), rel_tol=1e-12)
+    assert out[2] == np.abs(a - b).max()
+    assert out[3] == 0
+    a[0, 3, 4, 5] = np.nan
+    a[0, 1, 2, 3] = np.inf
+    with pytest.raises(etd.EtdError) as ei:
+        st.compare(st.field(a), st.field(b))
+    assert ei.value.status == etd.ETD_ENONFINITE
+    out = st.compare(st.field(a), st.field(b), allow_nonfinite=True)
+    assert out[3] == 2
+    st.close()
+
+
+def test_saturating_blowup_is_flagged(etd):
+    """u0 = 1 makes rho u/(1-u) infinite; the finite check reports it."""
+    import torch
+    p = W.Problem(dim=2, n=(40, 40), kappa=(1.0,), q=1.0, tau=0.01, reaction="saturating")
+    st = etd.Stepper(p)
+    u0 = 0.5 * W.sine_product(p)[None]
+    u0[0, 20, 20] = 1.0
+    u = st.field(u0)
+    st.advance(u, 1)
+    ref = st.field(u0)
+    with pytest.raises(etd.EtdError) as ei:
+        st.compare(u, ref)
+    assert ei.value.status == etd.ETD_ENONFINITE
+    st.close()

@@ -16,6 +16,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "etdo.c")
 _LIB = os.path.join(_HERE, "libetdo.so")
+# The same source built with x87 extended precision: a referee that shows how
+# much of a difference between two FP64 results is FP64 rounding.
+_LIB_EXT = os.path.join(_HERE, "libetdo_ext.so")
 
 _RXN = {
     "none": 0, "linear": 1, "fisher": 2, "allen_cahn": 3, "ac_mms": 4,
@@ -40,24 +43,26 @@ class _Problem(ctypes.Structure):
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP over independent lines)."""
-    if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-D_DEFAULT_SOURCE",
-               "-o", _LIB + ".tmp", _SRC, "-lm"]
-        subprocess.check_call(cmd, cwd=_HERE)
-        os.replace(_LIB + ".tmp", _LIB)
+    """Compile the oracle with gcc (-O2, OpenMP over independent lines), in
+    FP64 and in the extended-precision referee build."""
+    for out, extra in ((_LIB, []), (_LIB_EXT, ["-DETDO_EXTENDED"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+            cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-D_DEFAULT_SOURCE", *extra,
+                   "-o", out + ".tmp", _SRC, "-lm"]
+            subprocess.check_call(cmd, cwd=_HERE)
+            os.replace(out + ".tmp", out)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = ctypes.CDLL(_LIB)
+def lib(precision: str = "fp64"):
+    if precision not in _libs:
+        path = {"fp64": _LIB, "extended": _LIB_EXT}[precision]
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            build(force=False)
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER(_Problem)
         dp = ctypes.POINTER(ctypes.c_double)
         L.etdo_advance.argtypes = [P, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int]
@@ -65,8 +70,8 @@ def lib():
         L.etdo_reaction.argtypes = [P, ctypes.c_double, dp, dp]
         L.etdo_poles.argtypes = [ctypes.c_int, dp, dp]
         L.etdo_threads.argtypes = [ctypes.c_int]
-        _lib = L
-    return _lib
+        _libs[precision] = L
+    return _libs[precision]
 
 
 def _struct(p) -> _Problem:
@@ -99,10 +104,12 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def advance(p, u: np.ndarray, nsteps: int, t0: float = 0.0, nthreads: int = 0) -> np.ndarray:
-    """Return U after nsteps steps of the scheme from time t0 (input untouched)."""
+def advance(p, u: np.ndarray, nsteps: int, t0: float = 0.0, nthreads: int = 0,
+            precision: str = "fp64") -> np.ndarray:
+    """Return U after nsteps steps of the scheme from time t0 (input untouched).
+    precision="extended" runs the referee build (x87 extended arithmetic)."""
     out = _f64(u, p.shape).copy()
-    rc = lib().etdo_advance(ctypes.byref(_struct(p)), _ptr(out), float(t0), int(nsteps), int(nthreads))
+    rc = lib(precision).etdo_advance(ctypes.byref(_struct(p)), _ptr(out), float(t0), int(nsteps), int(nthreads))
     if rc != 0:
         raise ValueError("oracle rejected the problem")
     return out.reshape(p.shape)

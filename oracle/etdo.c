@@ -37,7 +37,27 @@
 #include <omp.h>
 #endif
 
+/* Working precision.  The oracle is FP64.  Built with -DETDO_EXTENDED the
+ * same source runs in x87 extended precision (64-bit significand); that build
+ * only referees how much of a difference between two FP64 results is FP64
+ * rounding.  The public entry points take and return doubles either way. */
+#ifdef ETDO_EXTENDED
+typedef long double real;
+typedef long double complex cplx;
+#define R_SIN sinl
+#define R_EXP expl
+#define R_CREAL creall
+#define R_CIMAG cimagl
+#define R_PI 3.141592653589793238462643383279502884L
+#else
+typedef double real;
 typedef double complex cplx;
+#define R_SIN sin
+#define R_EXP exp
+#define R_CREAL creal
+#define R_CIMAG cimag
+#define R_PI M_PI
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Rational families: poles and residues                                    */
@@ -49,7 +69,7 @@ typedef struct {
     cplx r[3][2];    /* r[l-1][k]: residue of Q_l (or R_l) at pole k */
 } rational_family;
 
-static cplx poly_eval(const double* c, int deg, cplx x) {
+static cplx poly_eval(const real* c, int deg, cplx x) {
     /* c[0] x^deg + ... + c[deg] */
     cplx v = c[0];
     for (int i = 1; i <= deg; ++i) v = v * x + c[i];
@@ -57,7 +77,7 @@ static cplx poly_eval(const double* c, int deg, cplx x) {
 }
 
 /* Roots of a monic real quartic by the Weierstrass (Durand-Kerner) iteration. */
-static void quartic_roots(const double* c, cplx roots[4]) {
+static void quartic_roots(const real* c, cplx roots[4]) {
     cplx z[4];
     const cplx seed = 0.4 + 0.9 * I;
     z[0] = 1.0;
@@ -77,16 +97,16 @@ static void make_family(int pade, rational_family* f) {
     memset(f, 0, sizeof(*f));
     if (pade == 4) {
         /* R_1 = 24/den, R_2 = (x^3+4x^2+12x+24)/den, R_3 = (x^3+3x^2+8x+12)/den */
-        const double den[5] = {1.0, 4.0, 12.0, 24.0, 24.0};
-        const double dden[4] = {4.0, 12.0, 24.0, 24.0};
-        const double num[3][4] = {{0.0, 0.0, 0.0, 24.0},
+        const real den[5] = {1.0, 4.0, 12.0, 24.0, 24.0};
+        const real dden[4] = {4.0, 12.0, 24.0, 24.0};
+        const real num[3][4] = {{0.0, 0.0, 0.0, 24.0},
                                   {1.0, 4.0, 12.0, 24.0},
                                   {1.0, 3.0, 8.0, 12.0}};
         cplx roots[4];
         quartic_roots(den, roots);
         int k = 0;
         for (int j = 0; j < 4 && k < 2; ++j)
-            if (cimag(roots[j]) > 0.0) f->s[k++] = roots[j];
+            if (R_CIMAG(roots[j]) > 0.0) f->s[k++] = roots[j];
         f->np = 2;
         for (int l = 0; l < 3; ++l)
             for (int kk = 0; kk < 2; ++kk)
@@ -104,13 +124,13 @@ int etdo_poles(int pade, double* out_s, double* out_r) {
     rational_family f;
     make_family(pade, &f);
     for (int k = 0; k < f.np; ++k) {
-        out_s[2 * k] = creal(f.s[k]);
-        out_s[2 * k + 1] = cimag(f.s[k]);
+        out_s[2 * k] = (double)R_CREAL(f.s[k]);
+        out_s[2 * k + 1] = (double)R_CIMAG(f.s[k]);
     }
     for (int l = 0; l < 3; ++l)
         for (int k = 0; k < f.np; ++k) {
-            out_r[2 * (l * f.np + k)] = creal(f.r[l][k]);
-            out_r[2 * (l * f.np + k) + 1] = cimag(f.r[l][k]);
+            out_r[2 * (l * f.np + k)] = (double)R_CREAL(f.r[l][k]);
+            out_r[2 * (l * f.np + k) + 1] = (double)R_CIMAG(f.r[l][k]);
         }
     return f.np;
 }
@@ -126,7 +146,7 @@ typedef struct {
     cplx* inv;      /* inverse pivots */
 } thomas_factor;
 
-static void thomas_setup(thomas_factor* t, int len, double diag_real, double off_real, cplx s) {
+static void thomas_setup(thomas_factor* t, int len, real diag_real, real off_real, cplx s) {
     const cplx a = diag_real - s;
     const cplx b = off_real;
     t->len = len;
@@ -198,12 +218,12 @@ static int ctx_init(ctx* c, const etdo_problem* p, int nthreads) {
     c->nthreads = etdo_threads(nthreads);
     make_family(p->pade, &c->fam);
     for (int d = 0; d < p->dim; ++d) {
-        const double h = (p->hi[d] - p->lo[d]) / (p->n[d] + 1);
+        const real h = ((real)p->hi[d] - (real)p->lo[d]) / (p->n[d] + 1);
         for (int cc = 0; cc < p->ncomp; ++cc) {
-            const double k = p->kappa[cc];
+            const real k = p->kappa[cc];
             /* tau * h^-2 * (2 kappa + q h^2/dim) on the diagonal, -tau kappa h^-2 off it */
-            const double diag = p->tau * (2.0 * k / (h * h) + p->q / p->dim);
-            const double off = -p->tau * k / (h * h);
+            const real diag = (real)p->tau * (2.0 * k / (h * h) + (real)p->q / p->dim);
+            const real off = -(real)p->tau * k / (h * h);
             for (int kp = 0; kp < c->fam.np; ++kp)
                 thomas_setup(&c->fac[d][cc][kp], p->n[d], diag, off, c->fam.s[kp]);
         }
@@ -253,8 +273,8 @@ static size_t line_offset(const ctx* c, int d, size_t L) {
 
 /* out = sum_k 2 Re( (tau A_d - s_k)^-1 (alpha_k g1 + beta_k g2) ) along d for
  * one component (g2 may be NULL). */
-static void apply_dir(const ctx* c, int d, int comp, const cplx* alpha, const double* g1,
-                      const cplx* beta, const double* g2, double* out) {
+static void apply_dir(const ctx* c, int d, int comp, const cplx* alpha, const real* g1,
+                      const cplx* beta, const real* g2, real* out) {
     size_t nlines, stride;
     int len;
     line_geometry(c, d, &nlines, &len, &stride);
@@ -277,7 +297,7 @@ static void apply_dir(const ctx* c, int d, int comp, const cplx* alpha, const do
                     y[i] = rhs;
                 }
                 thomas_solve(&c->fac[d][comp][k], y);
-                for (int i = 0; i < len; ++i) out[base + i * stride] += 2.0 * creal(y[i]);
+                for (int i = 0; i < len; ++i) out[base + i * stride] += 2.0 * R_CREAL(y[i]);
             }
         }
         free(y);
@@ -285,7 +305,7 @@ static void apply_dir(const ctx* c, int d, int comp, const cplx* alpha, const do
 }
 
 /* out = Q_ell(tau A_d) g for one component */
-static void apply_q(const ctx* c, int ell, int d, int comp, const double* g, double* out) {
+static void apply_q(const ctx* c, int ell, int d, int comp, const real* g, real* out) {
     apply_dir(c, d, comp, c->fam.r[ell - 1], g, NULL, NULL, out);
 }
 
@@ -293,16 +313,17 @@ static void apply_q(const ctx* c, int ell, int d, int comp, const double* g, dou
 /* Reactions                                                                 */
 /* ------------------------------------------------------------------------ */
 
-static double node(const etdo_problem* p, int d, int i) {
-    const double h = (p->hi[d] - p->lo[d]) / (p->n[d] + 1);
+static real node(const etdo_problem* p, int d, int i) {
+    const real h = ((real)p->hi[d] - (real)p->lo[d]) / (p->n[d] + 1);
     return p->lo[d] + (i + 1) * h;
 }
 
-int etdo_reaction(const etdo_problem* p, double t, const double* u, double* f) {
+static int reaction(const etdo_problem* p, real t, const real* u, real* f) {
     if (check_problem(p)) return -1;
     const int nx = p->n[0], ny = p->n[1], nz = p->dim == 3 ? p->n[2] : 1;
     const size_t np = (size_t)nx * ny * nz;
-    const double* a = p->rxn_param;
+    real a[8];
+    for (int i = 0; i < 8; ++i) a[i] = p->rxn_param[i];
     switch (p->rxn) {
     case ETDO_RXN_NONE:
         for (size_t i = 0; i < np; ++i) f[i] = 0.0;
@@ -322,29 +343,29 @@ int etdo_reaction(const etdo_problem* p, double t, const double* u, double* f) {
     case ETDO_RXN_AC_MMS: {
         /* exact solution ue = e^{-lam t} prod_d sin(pi (x_d-lo_d)/L_d); psi makes
          * u_t - kappa Lap u + q u = u(1-u^2) + psi hold for it (Example 5.1). */
-        const double lam = a[0];
-        double mu = 0.0;
+        const real lam = a[0];
+        real mu = 0.0;
         for (int d = 0; d < p->dim; ++d) {
-            const double L = p->hi[d] - p->lo[d];
+            const real L = (real)p->hi[d] - (real)p->lo[d];
             if (a[1] != 0.0) {
-                const double h = L / (p->n[d] + 1);
-                const double sn = sin(M_PI * h / (2.0 * L));
+                const real h = L / (p->n[d] + 1);
+                const real sn = R_SIN(R_PI * h / (2.0 * L));
                 mu += 4.0 / (h * h) * sn * sn;
             } else {
-                mu += (M_PI / L) * (M_PI / L);
+                mu += (R_PI / L) * (R_PI / L);
             }
         }
-        const double rate = -lam + p->kappa[0] * mu + p->q;
-        const double et = exp(-lam * t);
+        const real rate = -lam + (real)p->kappa[0] * mu + (real)p->q;
+        const real et = R_EXP(-lam * t);
         for (int z = 0; z < nz; ++z) {
-            const double sz = p->dim == 3 ? sin(M_PI * (node(p, 2, z) - p->lo[2]) / (p->hi[2] - p->lo[2])) : 1.0;
+            const real sz = p->dim == 3 ? R_SIN(R_PI * (node(p, 2, z) - p->lo[2]) / ((real)p->hi[2] - p->lo[2])) : 1.0;
             for (int y = 0; y < ny; ++y) {
-                const double sy = sin(M_PI * (node(p, 1, y) - p->lo[1]) / (p->hi[1] - p->lo[1]));
+                const real sy = R_SIN(R_PI * (node(p, 1, y) - p->lo[1]) / ((real)p->hi[1] - p->lo[1]));
                 for (int x = 0; x < nx; ++x) {
-                    const double sx = sin(M_PI * (node(p, 0, x) - p->lo[0]) / (p->hi[0] - p->lo[0]));
+                    const real sx = R_SIN(R_PI * (node(p, 0, x) - p->lo[0]) / ((real)p->hi[0] - p->lo[0]));
                     const size_t i = ((size_t)z * ny + y) * nx + x;
-                    const double ue = et * sx * sy * sz;
-                    const double psi = rate * ue - ue * (1.0 - ue * ue);
+                    const real ue = et * sx * sy * sz;
+                    const real psi = rate * ue - ue * (1.0 - ue * ue);
                     f[i] = u[i] * (1.0 - u[i] * u[i]) + psi;
                 }
             }
@@ -352,8 +373,8 @@ int etdo_reaction(const etdo_problem* p, double t, const double* u, double* f) {
         break;
     }
     case ETDO_RXN_FHN_CUBIC: {
-        const double* uu = u;
-        const double* vv = u + np;
+        const real* uu = u;
+        const real* vv = u + np;
         for (size_t i = 0; i < np; ++i) {
             f[i] = uu[i] * (1.0 - uu[i]) * (uu[i] - a[0]) - vv[i];
             f[np + i] = a[1] * (uu[i] - a[2] * vv[i]);
@@ -361,8 +382,8 @@ int etdo_reaction(const etdo_problem* p, double t, const double* u, double* f) {
         break;
     }
     case ETDO_RXN_FHN_CLASSIC: {
-        const double* uu = u;
-        const double* vv = u + np;
+        const real* uu = u;
+        const real* vv = u + np;
         for (size_t i = 0; i < np; ++i) {
             f[i] = uu[i] - uu[i] * uu[i] * uu[i] / 3.0 - vv[i];
             f[np + i] = a[0] * (uu[i] - a[1] * vv[i]);
@@ -375,6 +396,33 @@ int etdo_reaction(const etdo_problem* p, double t, const double* u, double* f) {
     return 0;
 }
 
+/* Field conversions between the public FP64 arrays and the working precision. */
+static real* to_real(const double* x, size_t n) {
+    real* r = (real*)malloc(sizeof(real) * n);
+    for (size_t i = 0; i < n; ++i) r[i] = x[i];
+    return r;
+}
+
+static void from_real(const real* r, double* x, size_t n) {
+    for (size_t i = 0; i < n; ++i) x[i] = (double)r[i];
+}
+
+static size_t field_size(const etdo_problem* p) {
+    return (size_t)p->n[0] * p->n[1] * (p->dim == 3 ? p->n[2] : 1) * p->ncomp;
+}
+
+int etdo_reaction(const etdo_problem* p, double t, const double* u, double* f) {
+    if (check_problem(p)) return -1;
+    const size_t n = field_size(p);
+    real* ur = to_real(u, n);
+    real* fr = (real*)malloc(sizeof(real) * n);
+    const int rc = reaction(p, t, ur, fr);
+    from_real(fr, f, n);
+    free(ur);
+    free(fr);
+    return rc;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Public entry points                                                       */
 /* ------------------------------------------------------------------------ */
@@ -385,23 +433,30 @@ int etdo_apply(const etdo_problem* p, int ell, int d, int comp, const double* g,
     if (ell < 1 || ell > 3 || !p || d < 0 || d >= p->dim || comp < 0 || comp >= p->ncomp)
         return -1;
     if (ctx_init(&c, p, nthreads)) return -1;
-    apply_q(&c, ell, d, comp, g + (size_t)comp * c.npts, out + (size_t)comp * c.npts);
+    const size_t n = c.npts;
+    real* gr = to_real(g + (size_t)comp * n, n);
+    real* orr = (real*)malloc(sizeof(real) * n);
+    apply_q(&c, ell, d, comp, gr, orr);
+    from_real(orr, out + (size_t)comp * n, n);
+    free(gr);
+    free(orr);
     ctx_free(&c);
     return 0;
 }
 
-int etdo_advance(const etdo_problem* p, double* u, double t0, int nsteps, int nthreads) {
+int etdo_advance(const etdo_problem* p, double* u_io, double t0, int nsteps, int nthreads) {
     ctx c;
     if (nsteps < 0) return -1;
     if (ctx_init(&c, p, nthreads)) return -1;
     const size_t N = c.npts * p->ncomp;
-    const double tau = p->tau;
-    double* F0 = (double*)malloc(sizeof(double) * N);
-    double* wa = (double*)malloc(sizeof(double) * N);  /* w1, then w3 */
-    double* wb = (double*)malloc(sizeof(double) * N);  /* w2, then w4 */
-    double* tmp = (double*)malloc(sizeof(double) * N);
-    double* W = (double*)malloc(sizeof(double) * N);
-    double* F1 = (double*)malloc(sizeof(double) * N);
+    const real tau = p->tau;
+    real* u = to_real(u_io, N);
+    real* F0 = (real*)malloc(sizeof(real) * N);
+    real* wa = (real*)malloc(sizeof(real) * N);  /* w1, then w3 */
+    real* wb = (real*)malloc(sizeof(real) * N);  /* w2, then w4 */
+    real* tmp = (real*)malloc(sizeof(real) * N);
+    real* W = (real*)malloc(sizeof(real) * N);
+    real* F1 = (real*)malloc(sizeof(real) * N);
     const cplx* r1 = c.fam.r[0];
     const cplx* r3 = c.fam.r[2];
     cplx tr2[2], tr3[2];
@@ -411,9 +466,9 @@ int etdo_advance(const etdo_problem* p, double* u, double t0, int nsteps, int nt
     }
 
     for (int step = 0; step < nsteps; ++step) {
-        const double tn = t0 + step * tau;
-        const double tn1 = t0 + (step + 1) * tau;
-        etdo_reaction(p, tn, u, F0);
+        const real tn = (real)t0 + step * tau;
+        const real tn1 = (real)t0 + (step + 1) * tau;
+        reaction(p, tn, u, F0);
         for (int cc = 0; cc < p->ncomp; ++cc) {
             const size_t o = (size_t)cc * c.npts;
             if (p->dim == 3) {
@@ -430,7 +485,7 @@ int etdo_advance(const etdo_problem* p, double* u, double t0, int nsteps, int nt
             /* x-lines: W = Q1 w3 + tau Q2 w4, one solve per pole */
             apply_dir(&c, 0, cc, r1, wa + o, tr2, wb + o, W + o);
         }
-        etdo_reaction(p, tn1, W, F1);
+        reaction(p, tn1, W, F1);
         for (size_t i = 0; i < N; ++i) tmp[i] = F1[i] - wb[i];
         for (int cc = 0; cc < p->ncomp; ++cc) {
             const size_t o = (size_t)cc * c.npts;
@@ -438,8 +493,9 @@ int etdo_advance(const etdo_problem* p, double* u, double t0, int nsteps, int nt
         }
         for (size_t i = 0; i < N; ++i) u[i] = W[i] + F1[i];
     }
+    from_real(u, u_io, N);
 
-    free(F0); free(wa); free(wb); free(tmp); free(W); free(F1);
+    free(u); free(F0); free(wa); free(wb); free(tmp); free(W); free(F1);
     ctx_free(&c);
     return 0;
 }

@@ -152,6 +152,68 @@ __device__ __forceinline__ void react(const RxnArgs& r, const T* u, T* f, int x,
 }
 
 // ---------------------------------------------------------------------------
+// Shared pieces of the stage kernels
+// ---------------------------------------------------------------------------
+
+// acc[r][q] += P[16(rb0+r) .. +16][:] . B_q over the whole contracted length
+// NP (a multiple of 16).  The A operand comes straight from the row-major P in
+// global memory (L2-resident, 32 contiguous bytes per lane per 16-wide K
+// block) and is double-buffered in registers one K block ahead; the B operand
+// of K block kb, values e = 0..3 of lane (li, lg) for k = 16kb + 4lg + e, is
+// produced by bfrag(q, kb).
+template <typename T, int RB, int NQ, typename BF>
+__device__ __forceinline__ void gemm_p(const T* __restrict__ P, int NP, int rb0, int li, int lg,
+                                       typename Vec4<T>::type (&acc)[RB][NQ], BF bfrag) {
+    typedef typename Vec4<T>::type T4;
+    const int nkb = NP >> 4;
+    const T* prow[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) prow[r] = P + long(16 * (rb0 + r) + li) * NP + 4 * lg;
+    T4 a_cur[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) a_cur[r] = *reinterpret_cast<const T4*>(prow[r]);
+    for (int kb = 0; kb < nkb; ++kb) {
+        const int kn = min(kb + 1, nkb - 1) * 16;
+        T4 a_nxt[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) a_nxt[r] = *reinterpret_cast<const T4*>(prow[r] + kn);
+        T4 b[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) b[q] = bfrag(q, kb);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) acc[r][q] = mfma4(a_cur[r][e], b[q][e], acc[r][q]);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) a_cur[r] = a_nxt[r];
+    }
+}
+
+template <typename T, int RB, int NQ>
+__device__ __forceinline__ void zero(typename Vec4<T>::type (&acc)[RB][NQ]) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[r][q] = typename Vec4<T>::type{0, 0, 0, 0};
+}
+
+// 16-byte vector of T
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+    typedef double __attribute__((ext_vector_type(2))) type;
+    static constexpr int n = 2;
+};
+template <>
+struct Vec16<float> {
+    typedef float __attribute__((ext_vector_type(4))) type;
+    static constexpr int n = 4;
+};
+
+// ---------------------------------------------------------------------------
 // Outer-mode stage: contraction along a strided direction (z, or y)
 // ---------------------------------------------------------------------------
 
@@ -171,160 +233,154 @@ struct OuterArgs {
     int npx, npy;        // padded x and y extents (node decoding)
     int dim;
     RxnArgs rxn;
+    const void* other;   // split systems: the other component's field (first stage), else null
+    int comp;            // split systems: the component this launch handles
 };
 
-// Workgroup: ceil(NP/64) waves; wave w owns output row blocks 4w..4w+3.
-// LDS: [2*NC arrays][NP rows][16 + pad] of T, first the inputs, then the
-// scaled spectral coefficients.
-template <typename T, int NC, bool FIRST>
-__global__ __launch_bounds__(256) void outer_stage(OuterArgs a) {
+// Reaction of component `comp` of a two-component system at one node, the
+// other component being read from `other` (split processing).
+template <typename T>
+__device__ __forceinline__ T react_coupled(const RxnArgs& r, int comp, T mine, T theirs) {
+    T fu, fv;
+    if (comp == 0) react2<T>(r, mine, theirs, fu, fv);
+    else react2<T>(r, theirs, mine, fu, fv);
+    return comp == 0 ? fu : fv;
+}
+
+// Workgroup: NP/(16 RB) waves over one tile of 16*CB columns; wave w owns
+// output row blocks RB*w .. RB*w+RB-1 for all CB column blocks (each P
+// fragment feeds 2*NC*CB MFMAs).  LDS: [2*NC arrays][NP rows][16*CB] of T,
+// first the inputs (and f of them), then the scaled spectral coefficients.
+template <typename T, int NC, bool FIRST, int RB, int CB, int MAXT>
+__global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
     typedef typename Vec4<T>::type T4;
+    typedef typename Vec16<T>::type TV;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int RS = 16 * CB;           // columns per tile
+    constexpr int VPR = RS / VN;          // 16-byte vectors per tile row
     constexpr int NA = 2 * NC;
-    constexpr int RS = 16 + kOuterRowPad;
+    constexpr int NQ = NA * CB;           // B fragments per K block
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* X = reinterpret_cast<T*>(smem_raw);
 
     const int NP = a.NP;
-    const int nrb = NP >> 4;
-    const long AST = long(NP) * RS;
+    const int AST = NP * RS;
     const int tid = threadIdx.x;
-    const int w = tid >> 6, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
     const int cb = blockIdx.x % a.ncb;
     const long bt = blockIdx.x / a.ncb;
-    const long gbase = bt * a.sb + long(cb) * 16;
+    const long gbase = bt * a.sb + long(cb) * RS;
     const T* __restrict__ in0 = static_cast<const T*>(a.in0);
     const T* __restrict__ in1 = static_cast<const T*>(a.in1);
     const T* __restrict__ P = static_cast<const T*>(a.P);
 
     // ---- stage the tile (and the reaction, for the first stage) ----
-    for (int e = tid; e < NP * 16; e += blockDim.x) {
-        const int k = e >> 4, j = e & 15;
-        const long gi = gbase + long(k) * a.sk + j;
+    const int nvec = NP * VPR;
+#pragma unroll 4
+    for (int v = tid; v < nvec; v += blockDim.x) {
+        const int k = v / VPR, j0 = (v - k * VPR) * VN;
+        const long gi = gbase + long(k) * a.sk + j0;
         if constexpr (FIRST) {
-            T u[NC], f[NC];
+            TV u[NC], f[NC], other;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) u[c] = in0[gi + c * a.sc];
-            int x, y, z;
-            const int col = cb * 16 + j;
-            if (a.dim == 3) {
-                z = k;
-                y = col / a.npx;
-                x = col - y * a.npx;
-            } else {
-                z = 0;
-                y = k;
-                x = col;
+            for (int c = 0; c < NC; ++c) u[c] = *reinterpret_cast<const TV*>(in0 + gi + c * a.sc);
+            if (NC == 1 && a.other) other = *reinterpret_cast<const TV*>(static_cast<const T*>(a.other) + gi);
+#pragma unroll
+            for (int t = 0; t < VN; ++t) {
+                int x, y, z;
+                const int col = cb * RS + j0 + t;
+                if (a.dim == 3) {
+                    z = k;
+                    y = col / a.npx;
+                    x = col - y * a.npx;
+                } else {
+                    z = 0;
+                    y = k;
+                    x = col;
+                }
+                T uu[NC], ff[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) uu[c] = u[c][t];
+                if (NC == 1 && a.other) ff[0] = react_coupled<T>(a.rxn, a.comp, uu[0], other[t]);
+                else react<T, NC>(a.rxn, uu, ff, x, y, z);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) f[c][t] = ff[c];
             }
-            react<T, NC>(a.rxn, u, f, x, y, z);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                X[c * AST + k * RS + j] = u[c];
-                X[(NC + c) * AST + k * RS + j] = f[c];
+                *reinterpret_cast<TV*>(X + c * AST + k * RS + j0) = u[c];
+                *reinterpret_cast<TV*>(X + (NC + c) * AST + k * RS + j0) = f[c];
             }
         } else {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                X[c * AST + k * RS + j] = in0[gi + c * a.sc];
-                X[(NC + c) * AST + k * RS + j] = in1[gi + c * a.sc];
+                *reinterpret_cast<TV*>(X + c * AST + k * RS + j0) = *reinterpret_cast<const TV*>(in0 + gi + c * a.sc);
+                *reinterpret_cast<TV*>(X + (NC + c) * AST + k * RS + j0) =
+                    *reinterpret_cast<const TV*>(in1 + gi + c * a.sc);
             }
         }
     }
     __syncthreads();
 
-    const int rb0 = 4 * w;
-    T4 acc[4][NA];
-    T4 res[4][NA];
+    const int rb0 = RB * w;
+    // fragment qq = array (qq / CB), column block (qq % CB)
+    auto bfrag = [&](int qq, int kb) {
+        const T* src = X + (qq / CB) * AST + (qq % CB) * 16 + li;
+        T4 b;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q < NA; ++q) {
-            acc[r][q] = T4{0, 0, 0, 0};
-            res[r][q] = T4{0, 0, 0, 0};
-        }
+        for (int e = 0; e < 4; ++e) b[e] = src[(16 * kb + 4 * lg + e) * RS];
+        return b;
+    };
+    // element (row of accumulator register e of block rb0+r, column li of block qq%CB) of array qq/CB
+    auto at = [&](int qq, int r, int e) -> T& {
+        return X[(qq / CB) * AST + (16 * (rb0 + r) + acc_row<T>(lg, e)) * RS + (qq % CB) * 16 + li];
+    };
+    T4 acc[RB][NQ];
+    T4 res[RB][NQ];
+    zero<T, RB, NQ>(acc);
 
     // ---- forward product S = P g (all arrays share the A operand) ----
-    for (int kb = 0; kb < nrb; ++kb) {
-        T4 av[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (rb0 + r < nrb)
-                av[r] = *reinterpret_cast<const T4*>(P + long(16 * (rb0 + r) + li) * NP + 16 * kb + 4 * lg);
-        T4 bv[NA];
-#pragma unroll
-        for (int q = 0; q < NA; ++q)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) bv[q][e] = X[q * AST + (16 * kb + 4 * lg + e) * RS + li];
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (rb0 + r < nrb)
-#pragma unroll
-                    for (int q = 0; q < NA; ++q) acc[r][q] = mfma4(av[r][e], bv[q][e], acc[r][q]);
-    }
+    gemm_p<T, RB, NQ>(P, NP, rb0, li, lg, acc, bfrag);
     // the inputs at this wave's output rows, for the increment-form epilogue
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (rb0 + r < nrb)
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
-            for (int q = 0; q < NA; ++q)
+        for (int qq = 0; qq < NQ; ++qq)
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    res[r][q][e] = X[q * AST + (16 * (rb0 + r) + acc_row<T>(lg, e)) * RS + li];
+            for (int e = 0; e < 4; ++e) res[r][qq][e] = at(qq, r, e);
     __syncthreads();
 
     // ---- Hadamard scaling by q1 - 1, coefficients back to LDS ----
     const T* __restrict__ dg = static_cast<const T*>(a.diag);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (rb0 + r < nrb)
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
-            for (int q = 0; q < NA; ++q) {
-                const T* dc = dg + (q % NC) * a.diag_cstride;
+        for (int qq = 0; qq < NQ; ++qq) {
+            const T* dc = dg + ((qq / CB) % NC) * a.diag_cstride + 16 * (rb0 + r);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = 16 * (rb0 + r) + acc_row<T>(lg, e);
-                    X[q * AST + row * RS + li] = acc[r][q][e] * dc[row];
-                }
-                acc[r][q] = T4{0, 0, 0, 0};
-            }
+            for (int e = 0; e < 4; ++e) at(qq, r, e) = acc[r][qq][e] * dc[acc_row<T>(lg, e)];
+        }
+    zero<T, RB, NQ>(acc);
     __syncthreads();
 
     // ---- backward product P S and the increment-form epilogue ----
-    for (int kb = 0; kb < nrb; ++kb) {
-        T4 av[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (rb0 + r < nrb)
-                av[r] = *reinterpret_cast<const T4*>(P + long(16 * (rb0 + r) + li) * NP + 16 * kb + 4 * lg);
-        T4 bv[NA];
-#pragma unroll
-        for (int q = 0; q < NA; ++q)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) bv[q][e] = X[q * AST + (16 * kb + 4 * lg + e) * RS + li];
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (rb0 + r < nrb)
-#pragma unroll
-                    for (int q = 0; q < NA; ++q) acc[r][q] = mfma4(av[r][e], bv[q][e], acc[r][q]);
-    }
+    gemm_p<T, RB, NQ>(P, NP, rb0, li, lg, acc, bfrag);
     T* __restrict__ out0 = static_cast<T*>(a.out0);
     T* __restrict__ out1 = static_cast<T*>(a.out1);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (rb0 + r < nrb)
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
-            for (int q = 0; q < NA; ++q) {
-                T* o = (q < NC ? out0 : out1) + (q % NC) * a.sc + gbase + li;
+        for (int qq = 0; qq < NQ; ++qq) {
+            const int q = qq / CB;
+            T* o = (q < NC ? out0 : out1) + (q % NC) * a.sc + gbase + (qq % CB) * 16 + li;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = 16 * (rb0 + r) + acc_row<T>(lg, e);
-                    o[long(row) * a.sk] = res[r][q][e] + acc[r][q][e];
-                }
+            for (int e = 0; e < 4; ++e) {
+                const int row = 16 * (rb0 + r) + acc_row<T>(lg, e);
+                o[long(row) * a.sk] = res[r][qq][e] + acc[r][qq][e];
             }
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -346,169 +402,316 @@ struct XArgs {
     RxnArgs rxn;          // at t_{n+1}
 };
 
-// Workgroup: ceil(NP/64) waves over 16 consecutive x-lines.  Wave w owns the
-// spectral/physical x rows 64w..64w+63 of every product.  LDS: [2*NC][16
-// lines][NP + pad]; arrays 0..NC-1 hold w3 then c then e, arrays NC..2NC-1
-// hold w4 then d.
-template <typename T, int NC>
-__global__ __launch_bounds__(256) void x_stage(XArgs a) {
+// Workgroup: NP/(16 RB) waves over 16*CB consecutive x-lines.  Wave w owns
+// the spectral/physical x rows of blocks RB*w .. RB*w+RB-1 of every product,
+// for all CB line blocks.  LDS: [2*NC][16*CB lines][NP + pad]; arrays 0..NC-1
+// hold w3, then c, then e; arrays NC..2NC-1 hold w4, then d.
+template <typename T, int NC, int RB, int CB, int MAXT>
+__global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
     typedef typename Vec4<T>::type T4;
+    typedef typename Vec16<T>::type TV;
+    constexpr int VN = Vec16<T>::n;
     constexpr int NA = 2 * NC;
+    constexpr int NL = 16 * CB;           // lines per tile
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* R = reinterpret_cast<T*>(smem_raw);
 
     const int NP = a.NP;
     const int RS = NP + kInnerRowPad;
-    const int AST = 16 * RS;
-    const int nrb = NP >> 4;
+    const int AST = NL * RS;
     const int tid = threadIdx.x;
-    const int w = tid >> 6, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int li = lane & 15, lg = lane >> 4;
+    const long line0 = long(blockIdx.x) * NL;
+    const T* __restrict__ w3 = static_cast<const T*>(a.w3);
+    const T* __restrict__ w4 = static_cast<const T*>(a.w4);
+    const T* __restrict__ P = static_cast<const T*>(a.P);
+    const T tau = T(a.tau);
+
+    // the tile's lines are one contiguous run of NL*NP elements
+    const int nvec = NL * NP / VN;
+    const int vpl = NP / VN;
+#pragma unroll 4
+    for (int v = tid; v < nvec; v += blockDim.x) {
+        const int j = v / vpl, x = (v - j * vpl) * VN;
+        const long gi = line0 * NP + long(v) * VN;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            *reinterpret_cast<TV*>(R + c * AST + j * RS + x) = *reinterpret_cast<const TV*>(w3 + c * a.sc + gi);
+            *reinterpret_cast<TV*>(R + (NC + c) * AST + j * RS + x) = *reinterpret_cast<const TV*>(w4 + c * a.sc + gi);
+        }
+    }
+    __syncthreads();
+
+    const int rb0 = RB * w;
+    // B fragment qq of arrays q0..: array q0 + qq/CB, line li + 16 (qq%CB), x = 16kb + 4lg .. +3
+    auto bfrag_from = [&](int q0) {
+        return [&, q0](int qq, int kb) {
+            return *reinterpret_cast<const T4*>(R + (q0 + qq / CB) * AST + (li + 16 * (qq % CB)) * RS + 16 * kb +
+                                                4 * lg);
+        };
+    };
+    // element (line li + 16 cb, x row of accumulator register e of block rb0+r) of array q
+    auto at = [&](int q, int cb, int r, int e) -> T& {
+        return R[q * AST + (li + 16 * cb) * RS + 16 * (rb0 + r) + acc_row<T>(lg, e)];
+    };
+    const T* __restrict__ dg = static_cast<const T*>(a.diag);
+
+    // res[r][q*CB + cb]: w3 (q < NC) and w4 (q >= NC) at this wave's x rows
+    T4 res[RB][NA * CB];
+    {
+        // ---- b1 = P w3, b2 = P w4 ----
+        T4 acc[RB][NA * CB];
+        zero<T, RB, NA * CB>(acc);
+        gemm_p<T, RB, NA * CB>(P, NP, rb0, li, lg, acc, bfrag_from(0));
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int qq = 0; qq < NA * CB; ++qq)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) res[r][qq][e] = at(qq / CB, qq % CB, r, e);
+        __syncthreads();
+        // ---- c = (q1 - 1) b1 + tau (q2 - 1) b2 into arrays 0..NC-1 ----
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const T* d1 = dg + c * a.diag_cstride + 16 * (rb0 + r);
+                const T* d2 = d1 + a.diag_sstride;
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int k = acc_row<T>(lg, e);
+                        at(c, cb, r, e) = d1[k] * acc[r][c * CB + cb][e] + d2[k] * acc[r][(NC + c) * CB + cb][e];
+                    }
+            }
+        __syncthreads();
+    }
+
+    // ---- W = w3 + tau w4 + P c; d = f(W) - w4; V = W + tau d/2 ----
+    T4 acc[RB][NC * CB];
+    zero<T, RB, NC * CB>(acc);
+    gemm_p<T, RB, NC * CB>(P, NP, rb0, li, lg, acc, bfrag_from(0));
+    T4 V[RB][NC * CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const long line = line0 + li + 16 * cb;
+        const int ly = int(line % a.npy), lz = int(line / a.npy);
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                T Wv[NC], F[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    Wv[c] = res[r][c * CB + cb][e] + tau * res[r][(NC + c) * CB + cb][e] + acc[r][c * CB + cb][e];
+                react<T, NC>(a.rxn, Wv, F, 16 * (rb0 + r) + acc_row<T>(lg, e), ly, lz);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const T d = F[c] - res[r][(NC + c) * CB + cb][e];
+                    at(NC + c, cb, r, e) = d;
+                    V[r][c * CB + cb][e] = Wv[c] + T(0.5) * tau * d;
+                }
+            }
+    }
+    zero<T, RB, NC * CB>(acc);
+    __syncthreads();
+
+    // ---- e = (q3 - 1/2) .* (P d) into arrays 0..NC-1 ----
+    gemm_p<T, RB, NC * CB>(P, NP, rb0, li, lg, acc, bfrag_from(NC));
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const T* d3 = dg + c * a.diag_cstride + 2 * a.diag_sstride + 16 * (rb0 + r);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) at(c, cb, r, e) = d3[acc_row<T>(lg, e)] * acc[r][c * CB + cb][e];
+        }
+    zero<T, RB, NC * CB>(acc);
+    __syncthreads();
+
+    // ---- U+ = V + tau P e ----
+    gemm_p<T, RB, NC * CB>(P, NP, rb0, li, lg, acc, bfrag_from(0));
+    T* __restrict__ out = static_cast<T*>(a.out);
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const long line = line0 + li + 16 * cb;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                T* o = out + c * a.sc + line * NP + 16 * (rb0 + r);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    o[acc_row<T>(lg, e)] = V[r][c * CB + cb][e] + tau * acc[r][c * CB + cb][e];
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x stage of a two-component system whose joint tile exceeds the LDS: one
+// component at a time, in two kernels around W (written to memory), because
+// the reaction at W couples the components pointwise.
+// ---------------------------------------------------------------------------
+
+struct XSplitArgs {
+    const void* w3;       // this component (a) / unused (b)
+    const void* w4;       // this component
+    const void* W;        // (b) W of component 0; component 1 at +sc
+    void* out;            // (a) W of this component; (b) U+ of this component
+    const void* P;
+    const void* diag;     // slot X1 of this component
+    long diag_sstride;
+    int NP;
+    long sc;
+    int comp;
+    int npy;
+    double tau;
+    RxnArgs rxn;          // at t_{n+1}
+};
+
+// (a) W = w3 + tau w4 + P ((q1 - 1) .* (P w3) + tau (q2 - 1) .* (P w4)).
+// LDS: [2][16 lines][NP + pad] (w3 then c, w4).
+template <typename T, int RB, int MAXT>
+__global__ __launch_bounds__(MAXT) void x_stage_w(XSplitArgs a) {
+    typedef typename Vec4<T>::type T4;
+    typedef typename Vec16<T>::type TV;
+    constexpr int VN = Vec16<T>::n;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* R = reinterpret_cast<T*>(smem_raw);
+    const int NP = a.NP;
+    const int RS = NP + kInnerRowPad;
+    const int AST = 16 * RS;
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
     const long line0 = long(blockIdx.x) * 16;
     const T* __restrict__ w3 = static_cast<const T*>(a.w3);
     const T* __restrict__ w4 = static_cast<const T*>(a.w4);
     const T* __restrict__ P = static_cast<const T*>(a.P);
     const T tau = T(a.tau);
-
-    for (int e = tid; e < 16 * NP; e += blockDim.x) {
-        const int j = e / NP, x = e - j * NP;
-        const long gi = (line0 + j) * NP + x;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            R[c * AST + j * RS + x] = w3[c * a.sc + gi];
-            R[(NC + c) * AST + j * RS + x] = w4[c * a.sc + gi];
-        }
+    const int vpl = NP / VN;
+#pragma unroll 4
+    for (int v = tid; v < 16 * vpl; v += blockDim.x) {
+        const int j = v / vpl, x = (v - j * vpl) * VN;
+        const long gi = line0 * NP + long(v) * VN;
+        *reinterpret_cast<TV*>(R + j * RS + x) = *reinterpret_cast<const TV*>(w3 + gi);
+        *reinterpret_cast<TV*>(R + AST + j * RS + x) = *reinterpret_cast<const TV*>(w4 + gi);
     }
     __syncthreads();
-
-    const int rb0 = 4 * w;
-    T4 acc[4][NA];
-    T4 res[4][NA];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q < NA; ++q) {
-            acc[r][q] = T4{0, 0, 0, 0};
-            res[r][q] = T4{0, 0, 0, 0};
-        }
-
-    // One contraction: acc[r][q] += P[rows of block rb0+r][:] . B_q, B_q read
-    // from LDS array q (lines x positions).
-    auto contract = [&](int q0, int nq) {
-        for (int kb = 0; kb < nrb; ++kb) {
-            T4 av[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (rb0 + r < nrb)
-                    av[r] = *reinterpret_cast<const T4*>(P + long(16 * (rb0 + r) + li) * NP + 16 * kb + 4 * lg);
-            T4 bv[NA];
-#pragma unroll
-            for (int q = 0; q < NA; ++q)
-                if (q < nq) bv[q] = *reinterpret_cast<const T4*>(R + (q0 + q) * AST + li * RS + 16 * kb + 4 * lg);
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (rb0 + r < nrb)
-#pragma unroll
-                        for (int q = 0; q < NA; ++q)
-                            if (q < nq) acc[r][q] = mfma4(av[r][e], bv[q][e], acc[r][q]);
-        }
+    const int rb0 = RB * w;
+    auto bfrag_from = [&](int q0) {
+        return [&, q0](int q, int kb) {
+            return *reinterpret_cast<const T4*>(R + (q0 + q) * AST + li * RS + 16 * kb + 4 * lg);
+        };
     };
-    // element (line li, x row of accumulator register e) of LDS array q
     auto at = [&](int q, int r, int e) -> T& { return R[q * AST + li * RS + 16 * (rb0 + r) + acc_row<T>(lg, e)]; };
-
-    // ---- b1 = P w3, b2 = P w4 ----
-    contract(0, NA);
-    // w3, w4 at this wave's x rows, for the increment-form epilogues
+    const T* __restrict__ d1 = static_cast<const T*>(a.diag);
+    const T* __restrict__ d2 = d1 + a.diag_sstride;
+    T4 res[RB][2];
+    {
+        T4 acc[RB][2];
+        zero<T, RB, 2>(acc);
+        gemm_p<T, RB, 2>(P, NP, rb0, li, lg, acc, bfrag_from(0));
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (rb0 + r < nrb)
+        for (int r = 0; r < RB; ++r)
 #pragma unroll
-            for (int q = 0; q < NA; ++q)
+            for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) res[r][q][e] = at(q, r, e);
-    __syncthreads();
-
-    const T* __restrict__ dg = static_cast<const T*>(a.diag);
-    // ---- c = (q1 - 1) b1 + tau (q2 - 1) b2 into arrays 0..NC-1 ----
+        __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (rb0 + r < nrb)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const T* d1 = dg + c * a.diag_cstride + 16 * (rb0 + r);
-                const T* d2 = d1 + a.diag_sstride;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int k = acc_row<T>(lg, e);
-                    at(c, r, e) = d1[k] * acc[r][c][e] + d2[k] * acc[r][NC + c][e];
-                }
-            }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q < NA; ++q) acc[r][q] = T4{0, 0, 0, 0};
-    __syncthreads();
-
-    // ---- W = w3 + tau w4 + P c; d = f(W) - w4; V = W + tau d/2 ----
-    contract(0, NC);
-    T4 V[4][NC];
-    const long line = line0 + li;
-    const int ly = int(line % a.npy), lz = int(line / a.npy);
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (rb0 + r < nrb) {
+        for (int r = 0; r < RB; ++r)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                T Wv[NC], F[NC];
-#pragma unroll
-                for (int c = 0; c < NC; ++c) Wv[c] = res[r][c][e] + tau * res[r][NC + c][e] + acc[r][c][e];
-                react<T, NC>(a.rxn, Wv, F, 16 * (rb0 + r) + acc_row<T>(lg, e), ly, lz);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const T d = F[c] - res[r][NC + c][e];
-                    at(NC + c, r, e) = d;
-                    V[r][c][e] = Wv[c] + T(0.5) * tau * d;
-                }
+                const int k = 16 * (rb0 + r) + acc_row<T>(lg, e);
+                at(0, r, e) = d1[k] * acc[r][0][e] + d2[k] * acc[r][1][e];
             }
+        __syncthreads();
+    }
+    T4 acc[RB][1];
+    zero<T, RB, 1>(acc);
+    gemm_p<T, RB, 1>(P, NP, rb0, li, lg, acc, bfrag_from(0));
+    T* __restrict__ o = static_cast<T*>(a.out) + (line0 + li) * NP;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            o[16 * (rb0 + r) + acc_row<T>(lg, e)] = res[r][0][e] + tau * res[r][1][e] + acc[r][0][e];
+}
+
+// (b) d = f_comp(W_u, W_v) - w4; U+ = W + tau d/2 + tau P ((q3 - 1/2) .* (P d)).
+// LDS: [2][16 lines][NP + pad] (d, then e).
+template <typename T, int RB, int MAXT>
+__global__ __launch_bounds__(MAXT) void x_stage_u(XSplitArgs a) {
+    typedef typename Vec4<T>::type T4;
+    typedef typename Vec16<T>::type TV;
+    constexpr int VN = Vec16<T>::n;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* R = reinterpret_cast<T*>(smem_raw);
+    const int NP = a.NP;
+    const int RS = NP + kInnerRowPad;
+    const int AST = 16 * RS;
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int li = lane & 15, lg = lane >> 4;
+    const long line0 = long(blockIdx.x) * 16;
+    const T* __restrict__ W0 = static_cast<const T*>(a.W);
+    const T* __restrict__ w4 = static_cast<const T*>(a.w4);
+    const T* __restrict__ P = static_cast<const T*>(a.P);
+    const T tau = T(a.tau);
+    const int vpl = NP / VN;
+#pragma unroll 4
+    for (int v = tid; v < 16 * vpl; v += blockDim.x) {
+        const int j = v / vpl, x = (v - j * vpl) * VN;
+        const long gi = line0 * NP + long(v) * VN;
+        const TV wu = *reinterpret_cast<const TV*>(W0 + gi);
+        const TV wv = *reinterpret_cast<const TV*>(W0 + a.sc + gi);
+        const TV b4 = *reinterpret_cast<const TV*>(w4 + gi);
+        TV d;
+#pragma unroll
+        for (int t = 0; t < VN; ++t) {
+            T fu, fv;
+            react2<T>(a.rxn, wu[t], wv[t], fu, fv);
+            d[t] = (a.comp == 0 ? fu : fv) - b4[t];
         }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q < NA; ++q) acc[r][q] = T4{0, 0, 0, 0};
+        *reinterpret_cast<TV*>(R + j * RS + x) = d;
+    }
     __syncthreads();
-
-    // ---- e = (q3 - 1/2) .* (P d) into arrays 0..NC-1 ----
-    contract(NC, NC);
+    const int rb0 = RB * w;
+    auto bfrag_from = [&](int q0) {
+        return [&, q0](int q, int kb) {
+            return *reinterpret_cast<const T4*>(R + (q0 + q) * AST + li * RS + 16 * kb + 4 * lg);
+        };
+    };
+    auto at = [&](int q, int r, int e) -> T& { return R[q * AST + li * RS + 16 * (rb0 + r) + acc_row<T>(lg, e)]; };
+    const T* __restrict__ d3 = static_cast<const T*>(a.diag) + 2 * a.diag_sstride;
+    T4 acc[RB][1];
+    zero<T, RB, 1>(acc);
+    gemm_p<T, RB, 1>(P, NP, rb0, li, lg, acc, bfrag_from(0));
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) at(1, r, e) = d3[16 * (rb0 + r) + acc_row<T>(lg, e)] * acc[r][0][e];
+    zero<T, RB, 1>(acc);
     __syncthreads();
+    gemm_p<T, RB, 1>(P, NP, rb0, li, lg, acc, bfrag_from(1));
+    const T* __restrict__ Wc = W0 + a.comp * a.sc + (line0 + li) * NP;
+    T* __restrict__ o = static_cast<T*>(a.out) + (line0 + li) * NP;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (rb0 + r < nrb)
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const T* d3 = dg + c * a.diag_cstride + 2 * a.diag_sstride + 16 * (rb0 + r);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) at(c, r, e) = d3[acc_row<T>(lg, e)] * acc[r][c][e];
-            }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q < NA; ++q) acc[r][q] = T4{0, 0, 0, 0};
-    __syncthreads();
-
-    // ---- U+ = V + tau P e ----
-    contract(0, NC);
-    T* __restrict__ out = static_cast<T*>(a.out);
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (rb0 + r < nrb)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                T* o = out + c * a.sc + line * NP + 16 * (rb0 + r);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) o[acc_row<T>(lg, e)] = V[r][c][e] + tau * acc[r][c][e];
-            }
+        for (int e = 0; e < 4; ++e) {
+            const int x = 16 * (rb0 + r) + acc_row<T>(lg, e);
+            o[x] = Wc[x] + T(0.5) * tau * at(0, r, e) + tau * acc[r][0][e];
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -657,8 +860,6 @@ RxnArgs rxn_args(const Plan& pl, const char* ws, double t) {
     return r;
 }
 
-int waves_for(int NP) { return (NP + 63) / 64; }
-
 // Raise a kernel's dynamic-LDS limit once per instantiation (the attribute
 // persists for the process).
 template <typename K>
@@ -670,26 +871,130 @@ hipError_t set_lds(K kernel, size_t bytes, size_t& done) {
     return e;
 }
 
-template <typename T, int NC, bool FIRST>
-etd_status launch_outer(const OuterArgs& a, long nblocks, hipStream_t s) {
-    const size_t lds = size_t(2 * NC) * a.NP * (16 + kOuterRowPad) * sizeof(T);
-    auto k = outer_stage<T, NC, FIRST>;
+// Tile shape.  Every wave owns RB = rows_per_wave(NP) 16-row blocks of each
+// product, so a tile needs NP/(16 RB) waves (at most 8 up to NP = 256, 16
+// beyond, with the matching launch bound).  The x stage spans two 16-line
+// blocks when its LDS footprint fits at NP <= 256 (each P fragment then
+// feeds twice the MFMAs; FP64 systems would spill registers and stay at one
+// block).  The outer stages keep one 16-column block in FP64, where two
+// workgroups per CU (64 KB LDS each at NP = 256) beat the wider tile, and
+// take two blocks in FP32.  Measured on the 255^3 workload.
+template <typename T, int NC>
+constexpr bool wide_tiles() { return sizeof(T) == 4 || NC == 1; }
+template <typename T, int NC>
+constexpr bool wide_outer_tiles() { return sizeof(T) == 4; }
+
+int tile_threads(int NP) { return 64 * (NP / (16 * rows_per_wave(NP))); }
+
+// Launch kern<RB, MAXT> for the padded length NP: (2, 512) up to 256,
+// (2, 1024) up to 512, (4, 1024) up to 1024.
+#define DISPATCH_SHAPE(NP, KERNEL, ...)                                   \
+    ((NP) <= 256 ? KERNEL(2, 512, __VA_ARGS__)                            \
+                 : ((NP) <= 512 ? KERNEL(2, 1024, __VA_ARGS__) : KERNEL(4, 1024, __VA_ARGS__)))
+
+template <typename T, int NC, bool FIRST, int RB, int CB, int MAXT>
+etd_status launch_outer_k(const OuterArgs& a, long nblocks, hipStream_t s) {
+    const size_t lds = outer_lds_bytes(a.NP, 2 * NC, CB, sizeof(T));
+    auto k = outer_stage<T, NC, FIRST, RB, CB, MAXT>;
     static size_t done = 0;
     HIP_TRY(set_lds(k, lds, done), "outer stage LDS attribute");
-    hipLaunchKernelGGL(k, dim3(unsigned(nblocks)), dim3(64 * waves_for(a.NP)), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(unsigned(nblocks)), dim3(tile_threads(a.NP)), lds, s, a);
     HIP_TRY(hipGetLastError(), "outer stage launch");
     return ETD_OK;
 }
 
-template <typename T, int NC>
-etd_status launch_x(const XArgs& a, long nblocks, hipStream_t s) {
-    const size_t lds = size_t(2 * NC) * 16 * (a.NP + kInnerRowPad) * sizeof(T);
-    auto k = x_stage<T, NC>;
+#define OUTER_K(RB, MAXT, T, NC, FIRST, CB, a, nb, s) launch_outer_k<T, NC, FIRST, RB, CB, MAXT>(a, nb, s)
+
+// One outer stage over all components.  a.ncb and nblocks count 16-column
+// blocks (halved for 32-wide tiles).  Systems whose joint tile exceeds the
+// LDS run one component per launch.
+template <typename T, int NC, bool FIRST>
+etd_status launch_outer(OuterArgs a, long nblocks, hipStream_t s) {
+    if (NC == 2 && !outer_fused(a.NP, NC, sizeof(T))) {
+        for (int c = 0; c < NC; ++c) {
+            OuterArgs b = a;
+            const long off = c * a.sc;
+            b.in0 = static_cast<const T*>(a.in0) + off;
+            b.in1 = FIRST ? nullptr : static_cast<const T*>(a.in1) + off;
+            b.out0 = static_cast<T*>(a.out0) + off;
+            b.out1 = static_cast<T*>(a.out1) + off;
+            b.diag = static_cast<const T*>(a.diag) + c * a.diag_cstride;
+            b.other = FIRST ? static_cast<const T*>(a.in0) + (1 - c) * a.sc : nullptr;
+            b.comp = c;
+            const etd_status st = DISPATCH_SHAPE(a.NP, OUTER_K, T, 1, FIRST, 1, b, nblocks, s);
+            if (st != ETD_OK) return st;
+        }
+        return ETD_OK;
+    }
+    if (wide_outer_tiles<T, NC>() && a.NP <= 256 && outer_lds_bytes(a.NP, 2 * NC, 2, sizeof(T)) <= kMaxLds) {
+        a.ncb /= 2;
+        return launch_outer_k<T, NC, FIRST, 2, 2, 512>(a, nblocks / 2, s);
+    }
+    return DISPATCH_SHAPE(a.NP, OUTER_K, T, NC, FIRST, 1, a, nblocks, s);
+}
+
+template <typename T, int NC, int RB, int CB, int MAXT>
+etd_status launch_x_k(const XArgs& a, long nlines, hipStream_t s) {
+    const size_t lds = x_lds_bytes(a.NP, 2 * NC, CB, sizeof(T));
+    auto k = x_stage<T, NC, RB, CB, MAXT>;
     static size_t done = 0;
     HIP_TRY(set_lds(k, lds, done), "x stage LDS attribute");
-    hipLaunchKernelGGL(k, dim3(unsigned(nblocks)), dim3(64 * waves_for(a.NP)), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(unsigned(nlines / (16 * CB))), dim3(tile_threads(a.NP)), lds, s, a);
     HIP_TRY(hipGetLastError(), "x stage launch");
     return ETD_OK;
+}
+
+#define X_K(RB, MAXT, T, NC, CB, a, nl, s) launch_x_k<T, NC, RB, CB, MAXT>(a, nl, s)
+
+template <typename T, int RB, int MAXT, bool SECOND>
+etd_status launch_xsplit_k(const XSplitArgs& a, long nlines, hipStream_t s) {
+    const size_t lds = x_lds_bytes(a.NP, 2, 1, sizeof(T));
+    auto k = SECOND ? x_stage_u<T, RB, MAXT> : x_stage_w<T, RB, MAXT>;
+    static size_t done = 0;
+    HIP_TRY(set_lds(k, lds, done), "split x stage LDS attribute");
+    hipLaunchKernelGGL(k, dim3(unsigned(nlines / 16)), dim3(tile_threads(a.NP)), lds, s, a);
+    HIP_TRY(hipGetLastError(), "split x stage launch");
+    return ETD_OK;
+}
+
+#define XS_K(RB, MAXT, T, SECOND, a, nl, s) launch_xsplit_k<T, RB, MAXT, SECOND>(a, nl, s)
+
+// The x stage over all components.  `scratch` receives W when a system is
+// split (its joint tile exceeds the LDS).
+template <typename T, int NC>
+etd_status launch_x(const XArgs& a, long nlines, T* scratch, hipStream_t s) {
+    if (NC == 2 && !x_fused(a.NP, NC, sizeof(T))) {
+        XSplitArgs b{};
+        b.P = a.P;
+        b.diag_sstride = a.diag_sstride;
+        b.NP = a.NP;
+        b.sc = a.sc;
+        b.npy = a.npy;
+        b.tau = a.tau;
+        b.rxn = a.rxn;
+        b.W = scratch;
+        for (int c = 0; c < NC; ++c) {
+            b.w3 = static_cast<const T*>(a.w3) + c * a.sc;
+            b.w4 = static_cast<const T*>(a.w4) + c * a.sc;
+            b.out = scratch + c * a.sc;
+            b.diag = static_cast<const T*>(a.diag) + c * a.diag_cstride;
+            b.comp = c;
+            const etd_status st = DISPATCH_SHAPE(a.NP, XS_K, T, false, b, nlines, s);
+            if (st != ETD_OK) return st;
+        }
+        for (int c = 0; c < NC; ++c) {
+            b.w4 = static_cast<const T*>(a.w4) + c * a.sc;
+            b.out = static_cast<T*>(a.out) + c * a.sc;
+            b.diag = static_cast<const T*>(a.diag) + c * a.diag_cstride;
+            b.comp = c;
+            const etd_status st = DISPATCH_SHAPE(a.NP, XS_K, T, true, b, nlines, s);
+            if (st != ETD_OK) return st;
+        }
+        return ETD_OK;
+    }
+    if (wide_tiles<T, NC>() && a.NP <= 256 && x_lds_bytes(a.NP, 2 * NC, 2, sizeof(T)) <= kMaxLds)
+        return launch_x_k<T, NC, 2, 2, 512>(a, nlines, s);
+    return DISPATCH_SHAPE(a.NP, X_K, T, NC, 1, a, nlines, s);
 }
 
 etd_status timer_mark(StageTimer& t, int kind, bool begin, hipStream_t s);
@@ -785,7 +1090,7 @@ etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int ns
         x.npy = py;
         x.tau = tau;
         x.rxn = rxn_args(pl, ws, tn1);
-        TIMED(2, (launch_x<T, NC>(x, long(py) * pz / 16, s)));
+        TIMED(2, (launch_x<T, NC>(x, long(py) * pz, pl.dim == 3 ? WA : WC, s)));
     }
     return ETD_OK;
 }

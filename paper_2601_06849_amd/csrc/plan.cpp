@@ -112,22 +112,26 @@ etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
     pl.nc = p.ncomp;
     for (int d = 0; d < 3; ++d) {
         pl.n[d] = d < p.dim ? p.n[d] : 1;
+        // multiples of 32; beyond 512 of 64 (four 16-row blocks per wave)
         pl.np[d] = d < p.dim ? round_up(pl.n[d], kPad) : 1;
+        if (pl.np[d] > 512) pl.np[d] = round_up(pl.n[d], 2 * kPad);
     }
     for (int d = 0; d < p.dim; ++d)
         if (pl.np[d] > kMaxPadded) {
-            msg << "padded direction " << d << " has " << pl.np[d] << " points; the fused stage kernels take at most "
+            msg << "padded direction " << d << " has " << pl.np[d] << " points; the stage kernels take at most "
                 << kMaxPadded;
             err = msg.str();
             return ETD_EUNSUPPORTED;
         }
     pl.elem = p.precision == ETD_FP64 ? 8 : 4;
     for (int d = 0; d < p.dim; ++d) {
+        // one component's tile (the split path) must fit; two waves' rows per 16
         const int NP = pl.np[d];
-        const size_t outer = size_t(2 * pl.nc) * NP * (16 + kOuterRowPad) * pl.elem;
-        const size_t inner = size_t(2 * pl.nc) * 16 * (NP + kInnerRowPad) * pl.elem;
-        if (outer > kMaxLds || inner > kMaxLds) {
-            err = "stage tile exceeds the LDS budget for this size, precision and component count";
+        const bool fits = d == 0 ? x_lds_bytes(NP, 2, 1, pl.elem) <= kMaxLds
+                                 : outer_lds_bytes(NP, 2, 1, pl.elem) <= kMaxLds;
+        if (!fits || NP / (16 * rows_per_wave(NP)) > kMaxWaves) {
+            msg << "padded direction " << d << " (" << NP << " points) exceeds the on-chip tile limits at this precision";
+            err = msg.str();
             return ETD_EUNSUPPORTED;
         }
     }

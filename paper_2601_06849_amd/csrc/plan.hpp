@@ -12,16 +12,32 @@
 namespace etdds {
 
 // Granularity of the padded grid: every direction is padded with zeros to a
-// multiple of 32 (one BF16 MFMA K-step; two FP64/FP32 16-row tiles).
+// multiple of 32 (one BF16 MFMA K-step; two FP64/FP32 16-row tiles), or of 64
+// beyond 512 points.
 constexpr int kPad = 32;
-// Largest padded direction the fused stage kernels support.
-constexpr int kMaxPadded = 256;
-// LDS budget of one stage workgroup (bytes).
+// Largest padded direction the stage kernels support.
+constexpr int kMaxPadded = 1024;
+// LDS budget of one stage workgroup (bytes) and its largest wave count.
 constexpr size_t kMaxLds = 160 * 1024;
-
-// Row strides (in elements) of the LDS tiles, padded against bank conflicts.
-constexpr int kOuterRowPad = 0;
+constexpr int kMaxWaves = 16;
+// Row padding (elements) of the x-stage LDS tiles, against bank conflicts.
 constexpr int kInnerRowPad = 4;
+
+// LDS footprint of an outer-stage tile (`arrays` fields of NP rows x 16*cb
+// columns) and of an x-stage tile (`arrays` fields of 16*cb lines x NP).
+inline size_t outer_lds_bytes(int NP, int arrays, int cb, size_t elem) {
+    return size_t(arrays) * NP * 16 * cb * elem;
+}
+inline size_t x_lds_bytes(int NP, int arrays, int cb, size_t elem) {
+    return size_t(arrays) * 16 * cb * (NP + kInnerRowPad) * elem;
+}
+// 16-row blocks per wave: a tile needs NP / (16 * rows_per_wave) waves.
+inline int rows_per_wave(int NP) { return NP <= 512 ? 2 : 4; }
+// Both components of a system share one tile when it fits in LDS; otherwise
+// each component is processed alone (the reaction reads the other one from
+// memory) and the x stage is split in two kernels around W.
+inline bool outer_fused(int NP, int nc, size_t elem) { return outer_lds_bytes(NP, 2 * nc, 1, elem) <= kMaxLds; }
+inline bool x_fused(int NP, int nc, size_t elem) { return x_lds_bytes(NP, 2 * nc, 1, elem) <= kMaxLds; }
 
 struct Layout {
     size_t P[3];        // eigenvector matrices (NP x NP, row-major; BF16X6: hi, mid, lo)

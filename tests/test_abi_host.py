@@ -136,11 +136,21 @@ def test_plan_rejects_malformed_problem(etd, mod):
     assert ei.value.status == etd.ETD_EINVAL
 
 
-def test_plan_reports_unsupported_sizes(etd):
-    p = W.Problem(dim=2, n=(300, 10), kappa=(0.1,), tau=0.01, reaction="fisher")
+@pytest.mark.parametrize("n,precision", [((1100, 10), "fp32"), ((10, 700), "fp64"), ((700, 10), "fp64")])
+def test_plan_reports_unsupported_sizes(etd, n, precision):
+    """Padded extents beyond 1024, or an FP64 tile of one component beyond the
+    LDS budget (extents above 576), are reported as unsupported."""
+    p = W.Problem(dim=2, n=n, kappa=(0.1,), tau=0.01, reaction="fisher", precision=precision)
     with pytest.raises(etd.EtdError) as ei:
         etd.etd_plan_create(p)
     assert ei.value.status == etd.ETD_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("n,precision", [((1023, 1023), "fp32"), ((576, 576), "fp64"), ((511, 511), "fp64")])
+def test_plan_accepts_large_supported_sizes(etd, n, precision):
+    p = W.Problem(dim=2, n=n, kappa=(0.1, 0.2), tau=0.01, reaction="fhn_cubic", precision=precision)
+    plan = etd.etd_plan_create(p)
+    etd.etd_plan_destroy(plan)
 
 
 def test_host_side_argument_errors_touch_nothing(etd):

@@ -100,6 +100,94 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+template <typename T, int N>
+using vec_t = T __attribute__((ext_vector_type(N)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// KL contiguous elements from LDS, read in 16-byte pieces.
+template <typename T, int KL>
+__device__ __forceinline__ vec_t<T, KL> lds_vec(const T* p) {
+    constexpr int PER = 16 / int(sizeof(T));
+    vec_t<T, KL> v;
+#pragma unroll
+    for (int i = 0; i < KL / PER; ++i) {
+        const vec_t<T, PER> w = *reinterpret_cast<const vec_t<T, PER>*>(p + i * PER);
+#pragma unroll
+        for (int j = 0; j < PER; ++j) v[i * PER + j] = w[j];
+    }
+    return v;
+}
+
+// How one 16x16 block of a mode product is computed.  A K block of KB
+// contracted indices is consumed in NSUB matrix-core steps; lane (i, g) of the
+// A operand holds P[row i][k0 .. k0+KL), k0 = KB*kb + KL*g, and lane (j, g) of
+// the B operand the same k range of column j.  row(g, e) gives the tile row of
+// accumulator register e in lane group g.
+//
+// Native: FP64 or FP32 16x16x4 MFMA, K block 16, four steps of 4.
+template <typename T>
+struct NativeMma {
+    typedef T elem;
+    static constexpr int KB = 16, KL = 4, NSUB = 4;
+    typedef vec_t<T, 4> A;
+    typedef vec_t<T, 4> B;
+    __device__ static A load_a(const void* P, int, long off) {
+        return *reinterpret_cast<const A*>(static_cast<const T*>(P) + off);
+    }
+    __device__ static B prep(const vec_t<T, 4>& b) { return b; }
+    __device__ static void step(vec_t<T, 4>& acc, const A& a, const B& b, int e) { acc = mfma4(a[e], b[e], acc); }
+    __device__ static int row(int g, int e) { return acc_row<T>(g, e); }
+};
+
+// Split BF16: both operands are written x = hi + mid + lo with bfloat16
+// pieces (hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid), each
+// subtraction exact in FP32); the product keeps the six terms whose weight is
+// at least 2^-16 of hi*hi (lo*hi, mid*mid, hi*lo, mid*hi, hi*mid, hi*hi, the
+// small ones first) on the BF16 16x16x32 MFMA with FP32 accumulation.  P's
+// pieces are split once on the host (three planes of NP*NP); the data's are
+// split on the fly.
+struct Bf16x6Mma {
+    typedef float elem;
+    static constexpr int KB = 32, KL = 8, NSUB = 6;
+    struct A {
+        bf16x8 p[3];   // hi, mid, lo
+    };
+    typedef A B;
+    __device__ static A load_a(const void* P, int NP, long off) {
+        const __bf16* q = static_cast<const __bf16*>(P) + off;
+        const long plane = long(NP) * NP;
+        A a;
+        a.p[0] = *reinterpret_cast<const bf16x8*>(q);
+        a.p[1] = *reinterpret_cast<const bf16x8*>(q + plane);
+        a.p[2] = *reinterpret_cast<const bf16x8*>(q + 2 * plane);
+        return a;
+    }
+    __device__ static B prep(const vec_t<float, 8>& x) {
+        B b;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const __bf16 h = (__bf16)x[e];
+            const float r1 = x[e] - float(h);
+            const __bf16 m = (__bf16)r1;
+            b.p[0][e] = h;
+            b.p[1][e] = m;
+            b.p[2][e] = (__bf16)(r1 - float(m));
+        }
+        return b;
+    }
+    __device__ static void step(f32x4& acc, const A& a, const B& b, int t) {
+        switch (t) {
+        case 0: acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[2], b.p[0], acc, 0, 0, 0); break;
+        case 1: acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[1], b.p[1], acc, 0, 0, 0); break;
+        case 2: acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[0], b.p[2], acc, 0, 0, 0); break;
+        case 3: acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[1], b.p[0], acc, 0, 0, 0); break;
+        case 4: acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[0], b.p[1], acc, 0, 0, 0); break;
+        default: acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[0], b.p[0], acc, 0, 0, 0); break;
+        }
+    }
+    __device__ static int row(int g, int e) { return 4 * g + e; }
+};
+
 // ---------------------------------------------------------------------------
 // Reactions (pointwise source terms of the examples and workloads)
 // ---------------------------------------------------------------------------
@@ -156,36 +244,35 @@ __device__ __forceinline__ void react(const RxnArgs& r, const T* u, T* f, int x,
 // ---------------------------------------------------------------------------
 
 // acc[r][q] += P[16(rb0+r) .. +16][:] . B_q over the whole contracted length
-// NP (a multiple of 16).  The A operand comes straight from the row-major P in
-// global memory (L2-resident, 32 contiguous bytes per lane per 16-wide K
-// block) and is double-buffered in registers one K block ahead; the B operand
-// of K block kb, values e = 0..3 of lane (li, lg) for k = 16kb + 4lg + e, is
-// produced by bfrag(q, kb).
-template <typename T, int RB, int NQ, typename BF>
-__device__ __forceinline__ void gemm_p(const T* __restrict__ P, int NP, int rb0, int li, int lg,
-                                       typename Vec4<T>::type (&acc)[RB][NQ], BF bfrag) {
-    typedef typename Vec4<T>::type T4;
-    const int nkb = NP >> 4;
-    const T* prow[RB];
+// NP (a multiple of M::KB).  The A operand comes straight from the row-major P
+// in global memory (L2-resident; each lane reads its KL contiguous entries)
+// and is double-buffered in registers one K block ahead; bload(q, k0) returns
+// the KL values of B fragment q for contracted indices k0 .. k0+KL of this
+// lane's column.
+template <typename M, int RB, int NQ, typename BL>
+__device__ __forceinline__ void gemm(const void* __restrict__ P, int NP, int rb0, int li, int lg,
+                                     vec_t<typename M::elem, 4> (&acc)[RB][NQ], BL bload) {
+    const int nkb = NP / M::KB;
+    long off[RB];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) prow[r] = P + long(16 * (rb0 + r) + li) * NP + 4 * lg;
-    T4 a_cur[RB];
+    for (int r = 0; r < RB; ++r) off[r] = long(16 * (rb0 + r) + li) * NP + M::KL * lg;
+    typename M::A a_cur[RB];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) a_cur[r] = *reinterpret_cast<const T4*>(prow[r]);
+    for (int r = 0; r < RB; ++r) a_cur[r] = M::load_a(P, NP, off[r]);
     for (int kb = 0; kb < nkb; ++kb) {
-        const int kn = min(kb + 1, nkb - 1) * 16;
-        T4 a_nxt[RB];
+        const int kn = min(kb + 1, nkb - 1) * M::KB;
+        typename M::A a_nxt[RB];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) a_nxt[r] = *reinterpret_cast<const T4*>(prow[r] + kn);
-        T4 b[NQ];
+        for (int r = 0; r < RB; ++r) a_nxt[r] = M::load_a(P, NP, off[r] + kn);
+        typename M::B b[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) b[q] = bfrag(q, kb);
+        for (int q = 0; q < NQ; ++q) b[q] = M::prep(bload(q, kb * M::KB + M::KL * lg));
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int t = 0; t < M::NSUB; ++t)
 #pragma unroll
             for (int r = 0; r < RB; ++r)
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) acc[r][q] = mfma4(a_cur[r][e], b[q][e], acc[r][q]);
+                for (int q = 0; q < NQ; ++q) M::step(acc[r][q], a_cur[r], b[q], t);
 #pragma unroll
         for (int r = 0; r < RB; ++r) a_cur[r] = a_nxt[r];
     }
@@ -251,8 +338,9 @@ __device__ __forceinline__ T react_coupled(const RxnArgs& r, int comp, T mine, T
 // output row blocks RB*w .. RB*w+RB-1 for all CB column blocks (each P
 // fragment feeds 2*NC*CB MFMAs).  LDS: [2*NC arrays][NP rows][16*CB] of T,
 // first the inputs (and f of them), then the scaled spectral coefficients.
-template <typename T, int NC, bool FIRST, int RB, int CB, int MAXT>
+template <typename M, int NC, bool FIRST, int RB, int CB, int MAXT>
 __global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
+    typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
@@ -274,7 +362,7 @@ __global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
     const long gbase = bt * a.sb + long(cb) * RS;
     const T* __restrict__ in0 = static_cast<const T*>(a.in0);
     const T* __restrict__ in1 = static_cast<const T*>(a.in1);
-    const T* __restrict__ P = static_cast<const T*>(a.P);
+    const void* __restrict__ P = a.P;
 
     // ---- stage the tile (and the reaction, for the first stage) ----
     const int nvec = NP * VPR;
@@ -326,23 +414,23 @@ __global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
 
     const int rb0 = RB * w;
     // fragment qq = array (qq / CB), column block (qq % CB)
-    auto bfrag = [&](int qq, int kb) {
+    auto bfrag = [&](int qq, int k0) {
         const T* src = X + (qq / CB) * AST + (qq % CB) * 16 + li;
-        T4 b;
+        vec_t<T, M::KL> b;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) b[e] = src[(16 * kb + 4 * lg + e) * RS];
+        for (int e = 0; e < M::KL; ++e) b[e] = src[(k0 + e) * RS];
         return b;
     };
     // element (row of accumulator register e of block rb0+r, column li of block qq%CB) of array qq/CB
     auto at = [&](int qq, int r, int e) -> T& {
-        return X[(qq / CB) * AST + (16 * (rb0 + r) + acc_row<T>(lg, e)) * RS + (qq % CB) * 16 + li];
+        return X[(qq / CB) * AST + (16 * (rb0 + r) + M::row(lg, e)) * RS + (qq % CB) * 16 + li];
     };
     T4 acc[RB][NQ];
     T4 res[RB][NQ];
     zero<T, RB, NQ>(acc);
 
     // ---- forward product S = P g (all arrays share the A operand) ----
-    gemm_p<T, RB, NQ>(P, NP, rb0, li, lg, acc, bfrag);
+    gemm<M, RB, NQ>(P, NP, rb0, li, lg, acc, bfrag);
     // the inputs at this wave's output rows, for the increment-form epilogue
 #pragma unroll
     for (int r = 0; r < RB; ++r)
@@ -360,13 +448,13 @@ __global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
         for (int qq = 0; qq < NQ; ++qq) {
             const T* dc = dg + ((qq / CB) % NC) * a.diag_cstride + 16 * (rb0 + r);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) at(qq, r, e) = acc[r][qq][e] * dc[acc_row<T>(lg, e)];
+            for (int e = 0; e < 4; ++e) at(qq, r, e) = acc[r][qq][e] * dc[M::row(lg, e)];
         }
     zero<T, RB, NQ>(acc);
     __syncthreads();
 
     // ---- backward product P S and the increment-form epilogue ----
-    gemm_p<T, RB, NQ>(P, NP, rb0, li, lg, acc, bfrag);
+    gemm<M, RB, NQ>(P, NP, rb0, li, lg, acc, bfrag);
     T* __restrict__ out0 = static_cast<T*>(a.out0);
     T* __restrict__ out1 = static_cast<T*>(a.out1);
 #pragma unroll
@@ -377,7 +465,7 @@ __global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
             T* o = (q < NC ? out0 : out1) + (q % NC) * a.sc + gbase + (qq % CB) * 16 + li;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = 16 * (rb0 + r) + acc_row<T>(lg, e);
+                const int row = 16 * (rb0 + r) + M::row(lg, e);
                 o[long(row) * a.sk] = res[r][qq][e] + acc[r][qq][e];
             }
         }
@@ -406,8 +494,9 @@ struct XArgs {
 // the spectral/physical x rows of blocks RB*w .. RB*w+RB-1 of every product,
 // for all CB line blocks.  LDS: [2*NC][16*CB lines][NP + pad]; arrays 0..NC-1
 // hold w3, then c, then e; arrays NC..2NC-1 hold w4, then d.
-template <typename T, int NC, int RB, int CB, int MAXT>
+template <typename M, int NC, int RB, int CB, int MAXT>
 __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
+    typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
@@ -426,7 +515,7 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
     const long line0 = long(blockIdx.x) * NL;
     const T* __restrict__ w3 = static_cast<const T*>(a.w3);
     const T* __restrict__ w4 = static_cast<const T*>(a.w4);
-    const T* __restrict__ P = static_cast<const T*>(a.P);
+    const void* __restrict__ P = a.P;
     const T tau = T(a.tau);
 
     // the tile's lines are one contiguous run of NL*NP elements
@@ -445,16 +534,15 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
     __syncthreads();
 
     const int rb0 = RB * w;
-    // B fragment qq of arrays q0..: array q0 + qq/CB, line li + 16 (qq%CB), x = 16kb + 4lg .. +3
+    // B fragment qq of arrays q0..: array q0 + qq/CB, line li + 16 (qq%CB), x = k0 .. k0+KL
     auto bfrag_from = [&](int q0) {
-        return [&, q0](int qq, int kb) {
-            return *reinterpret_cast<const T4*>(R + (q0 + qq / CB) * AST + (li + 16 * (qq % CB)) * RS + 16 * kb +
-                                                4 * lg);
+        return [&, q0](int qq, int k0) {
+            return lds_vec<T, M::KL>(R + (q0 + qq / CB) * AST + (li + 16 * (qq % CB)) * RS + k0);
         };
     };
     // element (line li + 16 cb, x row of accumulator register e of block rb0+r) of array q
     auto at = [&](int q, int cb, int r, int e) -> T& {
-        return R[q * AST + (li + 16 * cb) * RS + 16 * (rb0 + r) + acc_row<T>(lg, e)];
+        return R[q * AST + (li + 16 * cb) * RS + 16 * (rb0 + r) + M::row(lg, e)];
     };
     const T* __restrict__ dg = static_cast<const T*>(a.diag);
 
@@ -464,7 +552,7 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
         // ---- b1 = P w3, b2 = P w4 ----
         T4 acc[RB][NA * CB];
         zero<T, RB, NA * CB>(acc);
-        gemm_p<T, RB, NA * CB>(P, NP, rb0, li, lg, acc, bfrag_from(0));
+        gemm<M, RB, NA * CB>(P, NP, rb0, li, lg, acc, bfrag_from(0));
 #pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -483,7 +571,7 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
                 for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const int k = acc_row<T>(lg, e);
+                        const int k = M::row(lg, e);
                         at(c, cb, r, e) = d1[k] * acc[r][c * CB + cb][e] + d2[k] * acc[r][(NC + c) * CB + cb][e];
                     }
             }
@@ -493,7 +581,7 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
     // ---- W = w3 + tau w4 + P c; d = f(W) - w4; V = W + tau d/2 ----
     T4 acc[RB][NC * CB];
     zero<T, RB, NC * CB>(acc);
-    gemm_p<T, RB, NC * CB>(P, NP, rb0, li, lg, acc, bfrag_from(0));
+    gemm<M, RB, NC * CB>(P, NP, rb0, li, lg, acc, bfrag_from(0));
     T4 V[RB][NC * CB];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
@@ -507,7 +595,7 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
                     Wv[c] = res[r][c * CB + cb][e] + tau * res[r][(NC + c) * CB + cb][e] + acc[r][c * CB + cb][e];
-                react<T, NC>(a.rxn, Wv, F, 16 * (rb0 + r) + acc_row<T>(lg, e), ly, lz);
+                react<T, NC>(a.rxn, Wv, F, 16 * (rb0 + r) + M::row(lg, e), ly, lz);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const T d = F[c] - res[r][(NC + c) * CB + cb][e];
@@ -520,7 +608,7 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
     __syncthreads();
 
     // ---- e = (q3 - 1/2) .* (P d) into arrays 0..NC-1 ----
-    gemm_p<T, RB, NC * CB>(P, NP, rb0, li, lg, acc, bfrag_from(NC));
+    gemm<M, RB, NC * CB>(P, NP, rb0, li, lg, acc, bfrag_from(NC));
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < RB; ++r)
@@ -530,13 +618,13 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) at(c, cb, r, e) = d3[acc_row<T>(lg, e)] * acc[r][c * CB + cb][e];
+                for (int e = 0; e < 4; ++e) at(c, cb, r, e) = d3[M::row(lg, e)] * acc[r][c * CB + cb][e];
         }
     zero<T, RB, NC * CB>(acc);
     __syncthreads();
 
     // ---- U+ = V + tau P e ----
-    gemm_p<T, RB, NC * CB>(P, NP, rb0, li, lg, acc, bfrag_from(0));
+    gemm<M, RB, NC * CB>(P, NP, rb0, li, lg, acc, bfrag_from(0));
     T* __restrict__ out = static_cast<T*>(a.out);
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
@@ -548,7 +636,7 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
                 T* o = out + c * a.sc + line * NP + 16 * (rb0 + r);
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    o[acc_row<T>(lg, e)] = V[r][c * CB + cb][e] + tau * acc[r][c * CB + cb][e];
+                    o[M::row(lg, e)] = V[r][c * CB + cb][e] + tau * acc[r][c * CB + cb][e];
             }
     }
 }
@@ -577,8 +665,9 @@ struct XSplitArgs {
 
 // (a) W = w3 + tau w4 + P ((q1 - 1) .* (P w3) + tau (q2 - 1) .* (P w4)).
 // LDS: [2][16 lines][NP + pad] (w3 then c, w4).
-template <typename T, int RB, int MAXT>
+template <typename M, int RB, int MAXT>
 __global__ __launch_bounds__(MAXT) void x_stage_w(XSplitArgs a) {
+    typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
@@ -594,7 +683,7 @@ __global__ __launch_bounds__(MAXT) void x_stage_w(XSplitArgs a) {
     const long line0 = long(blockIdx.x) * 16;
     const T* __restrict__ w3 = static_cast<const T*>(a.w3);
     const T* __restrict__ w4 = static_cast<const T*>(a.w4);
-    const T* __restrict__ P = static_cast<const T*>(a.P);
+    const void* __restrict__ P = a.P;
     const T tau = T(a.tau);
     const int vpl = NP / VN;
 #pragma unroll 4
@@ -607,18 +696,16 @@ __global__ __launch_bounds__(MAXT) void x_stage_w(XSplitArgs a) {
     __syncthreads();
     const int rb0 = RB * w;
     auto bfrag_from = [&](int q0) {
-        return [&, q0](int q, int kb) {
-            return *reinterpret_cast<const T4*>(R + (q0 + q) * AST + li * RS + 16 * kb + 4 * lg);
-        };
+        return [&, q0](int q, int k0) { return lds_vec<T, M::KL>(R + (q0 + q) * AST + li * RS + k0); };
     };
-    auto at = [&](int q, int r, int e) -> T& { return R[q * AST + li * RS + 16 * (rb0 + r) + acc_row<T>(lg, e)]; };
+    auto at = [&](int q, int r, int e) -> T& { return R[q * AST + li * RS + 16 * (rb0 + r) + M::row(lg, e)]; };
     const T* __restrict__ d1 = static_cast<const T*>(a.diag);
     const T* __restrict__ d2 = d1 + a.diag_sstride;
     T4 res[RB][2];
     {
         T4 acc[RB][2];
         zero<T, RB, 2>(acc);
-        gemm_p<T, RB, 2>(P, NP, rb0, li, lg, acc, bfrag_from(0));
+        gemm<M, RB, 2>(P, NP, rb0, li, lg, acc, bfrag_from(0));
 #pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -630,26 +717,27 @@ __global__ __launch_bounds__(MAXT) void x_stage_w(XSplitArgs a) {
         for (int r = 0; r < RB; ++r)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int k = 16 * (rb0 + r) + acc_row<T>(lg, e);
+                const int k = 16 * (rb0 + r) + M::row(lg, e);
                 at(0, r, e) = d1[k] * acc[r][0][e] + d2[k] * acc[r][1][e];
             }
         __syncthreads();
     }
     T4 acc[RB][1];
     zero<T, RB, 1>(acc);
-    gemm_p<T, RB, 1>(P, NP, rb0, li, lg, acc, bfrag_from(0));
+    gemm<M, RB, 1>(P, NP, rb0, li, lg, acc, bfrag_from(0));
     T* __restrict__ o = static_cast<T*>(a.out) + (line0 + li) * NP;
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-            o[16 * (rb0 + r) + acc_row<T>(lg, e)] = res[r][0][e] + tau * res[r][1][e] + acc[r][0][e];
+            o[16 * (rb0 + r) + M::row(lg, e)] = res[r][0][e] + tau * res[r][1][e] + acc[r][0][e];
 }
 
 // (b) d = f_comp(W_u, W_v) - w4; U+ = W + tau d/2 + tau P ((q3 - 1/2) .* (P d)).
 // LDS: [2][16 lines][NP + pad] (d, then e).
-template <typename T, int RB, int MAXT>
+template <typename M, int RB, int MAXT>
 __global__ __launch_bounds__(MAXT) void x_stage_u(XSplitArgs a) {
+    typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
@@ -665,7 +753,7 @@ __global__ __launch_bounds__(MAXT) void x_stage_u(XSplitArgs a) {
     const long line0 = long(blockIdx.x) * 16;
     const T* __restrict__ W0 = static_cast<const T*>(a.W);
     const T* __restrict__ w4 = static_cast<const T*>(a.w4);
-    const T* __restrict__ P = static_cast<const T*>(a.P);
+    const void* __restrict__ P = a.P;
     const T tau = T(a.tau);
     const int vpl = NP / VN;
 #pragma unroll 4
@@ -687,29 +775,27 @@ __global__ __launch_bounds__(MAXT) void x_stage_u(XSplitArgs a) {
     __syncthreads();
     const int rb0 = RB * w;
     auto bfrag_from = [&](int q0) {
-        return [&, q0](int q, int kb) {
-            return *reinterpret_cast<const T4*>(R + (q0 + q) * AST + li * RS + 16 * kb + 4 * lg);
-        };
+        return [&, q0](int q, int k0) { return lds_vec<T, M::KL>(R + (q0 + q) * AST + li * RS + k0); };
     };
-    auto at = [&](int q, int r, int e) -> T& { return R[q * AST + li * RS + 16 * (rb0 + r) + acc_row<T>(lg, e)]; };
+    auto at = [&](int q, int r, int e) -> T& { return R[q * AST + li * RS + 16 * (rb0 + r) + M::row(lg, e)]; };
     const T* __restrict__ d3 = static_cast<const T*>(a.diag) + 2 * a.diag_sstride;
     T4 acc[RB][1];
     zero<T, RB, 1>(acc);
-    gemm_p<T, RB, 1>(P, NP, rb0, li, lg, acc, bfrag_from(0));
+    gemm<M, RB, 1>(P, NP, rb0, li, lg, acc, bfrag_from(0));
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) at(1, r, e) = d3[16 * (rb0 + r) + acc_row<T>(lg, e)] * acc[r][0][e];
+        for (int e = 0; e < 4; ++e) at(1, r, e) = d3[16 * (rb0 + r) + M::row(lg, e)] * acc[r][0][e];
     zero<T, RB, 1>(acc);
     __syncthreads();
-    gemm_p<T, RB, 1>(P, NP, rb0, li, lg, acc, bfrag_from(1));
+    gemm<M, RB, 1>(P, NP, rb0, li, lg, acc, bfrag_from(1));
     const T* __restrict__ Wc = W0 + a.comp * a.sc + (line0 + li) * NP;
     T* __restrict__ o = static_cast<T*>(a.out) + (line0 + li) * NP;
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int x = 16 * (rb0 + r) + acc_row<T>(lg, e);
+            const int x = 16 * (rb0 + r) + M::row(lg, e);
             o[x] = Wc[x] + T(0.5) * tau * at(0, r, e) + tau * acc[r][0][e];
         }
 }
@@ -892,10 +978,11 @@ int tile_threads(int NP) { return 64 * (NP / (16 * rows_per_wave(NP))); }
     ((NP) <= 256 ? KERNEL(2, 512, __VA_ARGS__)                            \
                  : ((NP) <= 512 ? KERNEL(2, 1024, __VA_ARGS__) : KERNEL(4, 1024, __VA_ARGS__)))
 
-template <typename T, int NC, bool FIRST, int RB, int CB, int MAXT>
+template <typename M, int NC, bool FIRST, int RB, int CB, int MAXT>
 etd_status launch_outer_k(const OuterArgs& a, long nblocks, hipStream_t s) {
+    typedef typename M::elem T;
     const size_t lds = outer_lds_bytes(a.NP, 2 * NC, CB, sizeof(T));
-    auto k = outer_stage<T, NC, FIRST, RB, CB, MAXT>;
+    auto k = outer_stage<M, NC, FIRST, RB, CB, MAXT>;
     static size_t done = 0;
     HIP_TRY(set_lds(k, lds, done), "outer stage LDS attribute");
     hipLaunchKernelGGL(k, dim3(unsigned(nblocks)), dim3(tile_threads(a.NP)), lds, s, a);
@@ -903,13 +990,14 @@ etd_status launch_outer_k(const OuterArgs& a, long nblocks, hipStream_t s) {
     return ETD_OK;
 }
 
-#define OUTER_K(RB, MAXT, T, NC, FIRST, CB, a, nb, s) launch_outer_k<T, NC, FIRST, RB, CB, MAXT>(a, nb, s)
+#define OUTER_K(RB, MAXT, M, NC, FIRST, CB, a, nb, s) launch_outer_k<M, NC, FIRST, RB, CB, MAXT>(a, nb, s)
 
 // One outer stage over all components.  a.ncb and nblocks count 16-column
 // blocks (halved for 32-wide tiles).  Systems whose joint tile exceeds the
 // LDS run one component per launch.
-template <typename T, int NC, bool FIRST>
+template <typename M, int NC, bool FIRST>
 etd_status launch_outer(OuterArgs a, long nblocks, hipStream_t s) {
+    typedef typename M::elem T;
     if (NC == 2 && !outer_fused(a.NP, NC, sizeof(T))) {
         for (int c = 0; c < NC; ++c) {
             OuterArgs b = a;
@@ -921,22 +1009,23 @@ etd_status launch_outer(OuterArgs a, long nblocks, hipStream_t s) {
             b.diag = static_cast<const T*>(a.diag) + c * a.diag_cstride;
             b.other = FIRST ? static_cast<const T*>(a.in0) + (1 - c) * a.sc : nullptr;
             b.comp = c;
-            const etd_status st = DISPATCH_SHAPE(a.NP, OUTER_K, T, 1, FIRST, 1, b, nblocks, s);
+            const etd_status st = DISPATCH_SHAPE(a.NP, OUTER_K, M, 1, FIRST, 1, b, nblocks, s);
             if (st != ETD_OK) return st;
         }
         return ETD_OK;
     }
     if (wide_outer_tiles<T, NC>() && a.NP <= 256 && outer_lds_bytes(a.NP, 2 * NC, 2, sizeof(T)) <= kMaxLds) {
         a.ncb /= 2;
-        return launch_outer_k<T, NC, FIRST, 2, 2, 512>(a, nblocks / 2, s);
+        return launch_outer_k<M, NC, FIRST, 2, 2, 512>(a, nblocks / 2, s);
     }
-    return DISPATCH_SHAPE(a.NP, OUTER_K, T, NC, FIRST, 1, a, nblocks, s);
+    return DISPATCH_SHAPE(a.NP, OUTER_K, M, NC, FIRST, 1, a, nblocks, s);
 }
 
-template <typename T, int NC, int RB, int CB, int MAXT>
+template <typename M, int NC, int RB, int CB, int MAXT>
 etd_status launch_x_k(const XArgs& a, long nlines, hipStream_t s) {
+    typedef typename M::elem T;
     const size_t lds = x_lds_bytes(a.NP, 2 * NC, CB, sizeof(T));
-    auto k = x_stage<T, NC, RB, CB, MAXT>;
+    auto k = x_stage<M, NC, RB, CB, MAXT>;
     static size_t done = 0;
     HIP_TRY(set_lds(k, lds, done), "x stage LDS attribute");
     hipLaunchKernelGGL(k, dim3(unsigned(nlines / (16 * CB))), dim3(tile_threads(a.NP)), lds, s, a);
@@ -944,12 +1033,13 @@ etd_status launch_x_k(const XArgs& a, long nlines, hipStream_t s) {
     return ETD_OK;
 }
 
-#define X_K(RB, MAXT, T, NC, CB, a, nl, s) launch_x_k<T, NC, RB, CB, MAXT>(a, nl, s)
+#define X_K(RB, MAXT, M, NC, CB, a, nl, s) launch_x_k<M, NC, RB, CB, MAXT>(a, nl, s)
 
-template <typename T, int RB, int MAXT, bool SECOND>
+template <typename M, int RB, int MAXT, bool SECOND>
 etd_status launch_xsplit_k(const XSplitArgs& a, long nlines, hipStream_t s) {
+    typedef typename M::elem T;
     const size_t lds = x_lds_bytes(a.NP, 2, 1, sizeof(T));
-    auto k = SECOND ? x_stage_u<T, RB, MAXT> : x_stage_w<T, RB, MAXT>;
+    auto k = SECOND ? x_stage_u<M, RB, MAXT> : x_stage_w<M, RB, MAXT>;
     static size_t done = 0;
     HIP_TRY(set_lds(k, lds, done), "split x stage LDS attribute");
     hipLaunchKernelGGL(k, dim3(unsigned(nlines / 16)), dim3(tile_threads(a.NP)), lds, s, a);
@@ -957,12 +1047,13 @@ etd_status launch_xsplit_k(const XSplitArgs& a, long nlines, hipStream_t s) {
     return ETD_OK;
 }
 
-#define XS_K(RB, MAXT, T, SECOND, a, nl, s) launch_xsplit_k<T, RB, MAXT, SECOND>(a, nl, s)
+#define XS_K(RB, MAXT, M, SECOND, a, nl, s) launch_xsplit_k<M, RB, MAXT, SECOND>(a, nl, s)
 
 // The x stage over all components.  `scratch` receives W when a system is
 // split (its joint tile exceeds the LDS).
-template <typename T, int NC>
-etd_status launch_x(const XArgs& a, long nlines, T* scratch, hipStream_t s) {
+template <typename M, int NC>
+etd_status launch_x(const XArgs& a, long nlines, typename M::elem* scratch, hipStream_t s) {
+    typedef typename M::elem T;
     if (NC == 2 && !x_fused(a.NP, NC, sizeof(T))) {
         XSplitArgs b{};
         b.P = a.P;
@@ -979,7 +1070,7 @@ etd_status launch_x(const XArgs& a, long nlines, T* scratch, hipStream_t s) {
             b.out = scratch + c * a.sc;
             b.diag = static_cast<const T*>(a.diag) + c * a.diag_cstride;
             b.comp = c;
-            const etd_status st = DISPATCH_SHAPE(a.NP, XS_K, T, false, b, nlines, s);
+            const etd_status st = DISPATCH_SHAPE(a.NP, XS_K, M, false, b, nlines, s);
             if (st != ETD_OK) return st;
         }
         for (int c = 0; c < NC; ++c) {
@@ -987,14 +1078,14 @@ etd_status launch_x(const XArgs& a, long nlines, T* scratch, hipStream_t s) {
             b.out = static_cast<T*>(a.out) + c * a.sc;
             b.diag = static_cast<const T*>(a.diag) + c * a.diag_cstride;
             b.comp = c;
-            const etd_status st = DISPATCH_SHAPE(a.NP, XS_K, T, true, b, nlines, s);
+            const etd_status st = DISPATCH_SHAPE(a.NP, XS_K, M, true, b, nlines, s);
             if (st != ETD_OK) return st;
         }
         return ETD_OK;
     }
     if (wide_tiles<T, NC>() && a.NP <= 256 && x_lds_bytes(a.NP, 2 * NC, 2, sizeof(T)) <= kMaxLds)
-        return launch_x_k<T, NC, 2, 2, 512>(a, nlines, s);
-    return DISPATCH_SHAPE(a.NP, X_K, T, NC, 1, a, nlines, s);
+        return launch_x_k<M, NC, 2, 2, 512>(a, nlines, s);
+    return DISPATCH_SHAPE(a.NP, X_K, M, NC, 1, a, nlines, s);
 }
 
 etd_status timer_mark(StageTimer& t, int kind, bool begin, hipStream_t s);
@@ -1009,8 +1100,9 @@ etd_status timer_mark(StageTimer& t, int kind, bool begin, hipStream_t s);
         if (st_ != ETD_OK) return st_;                              \
     } while (0)
 
-template <typename T, int NC>
+template <typename M, int NC>
 etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int nsteps, hipStream_t s) {
+    typedef typename M::elem T;
     const int px = pl.np[0], py = pl.np[1], pz = pl.np[2];
     const long sc = long(px) * py * pz;
     T* U = reinterpret_cast<T*>(ws + pl.lay.field[0]);
@@ -1047,7 +1139,7 @@ etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int ns
             o.ncb = px * py / 16;
             o.sk = long(px) * py;
             o.sb = 0;
-            TIMED(0, (launch_outer<T, NC, true>(o, o.ncb, s)));
+            TIMED(0, (launch_outer<M, NC, true>(o, o.ncb, s)));
             // y stage: contracted index y (stride px), columns x, batches z
             o.in0 = WA;
             o.in1 = WB;
@@ -1059,7 +1151,7 @@ etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int ns
             o.ncb = px / 16;
             o.sk = px;
             o.sb = long(px) * py;
-            TIMED(1, (launch_outer<T, NC, false>(o, long(o.ncb) * pz, s)));
+            TIMED(1, (launch_outer<M, NC, false>(o, long(o.ncb) * pz, s)));
             w3 = WC;
             w4 = WD;
         } else {
@@ -1073,7 +1165,7 @@ etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int ns
             o.ncb = px / 16;
             o.sk = px;
             o.sb = 0;
-            TIMED(0, (launch_outer<T, NC, true>(o, o.ncb, s)));
+            TIMED(0, (launch_outer<M, NC, true>(o, o.ncb, s)));
             w3 = WA;
             w4 = WB;
         }
@@ -1090,18 +1182,19 @@ etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int ns
         x.npy = py;
         x.tau = tau;
         x.rxn = rxn_args(pl, ws, tn1);
-        TIMED(2, (launch_x<T, NC>(x, long(py) * pz, pl.dim == 3 ? WA : WC, s)));
+        TIMED(2, (launch_x<M, NC>(x, long(py) * pz, pl.dim == 3 ? WA : WC, s)));
     }
     return ETD_OK;
 }
 
-template <typename T>
-etd_status advance_t(const Plan& pl, StageTimer& tm, void* u, double t0, int nsteps, char* ws, hipStream_t s) {
+template <typename M>
+etd_status advance_m(const Plan& pl, StageTimer& tm, void* u, double t0, int nsteps, char* ws, hipStream_t s) {
+    typedef typename M::elem T;
     const Dims d = dims_of(pl);
     T* U = reinterpret_cast<T*>(ws + pl.lay.field[0]);
     hipLaunchKernelGGL(pack_field<T>, dim3(2048), dim3(256), 0, s, static_cast<const T*>(u), U, d);
     HIP_TRY(hipGetLastError(), "pack launch");
-    etd_status st = pl.nc == 1 ? run_steps<T, 1>(pl, tm, ws, t0, nsteps, s) : run_steps<T, 2>(pl, tm, ws, t0, nsteps, s);
+    etd_status st = pl.nc == 1 ? run_steps<M, 1>(pl, tm, ws, t0, nsteps, s) : run_steps<M, 2>(pl, tm, ws, t0, nsteps, s);
     if (st != ETD_OK) return st;
     hipLaunchKernelGGL(unpack_field<T>, dim3(2048), dim3(256), 0, s, U, static_cast<T*>(u), d);
     HIP_TRY(hipGetLastError(), "unpack launch");
@@ -1148,10 +1241,6 @@ etd_status etd_plan_create(const etd_problem* prob, etd_plan** out) {
         delete p;
         return fail(st, err);
     }
-    if (prob->precision == ETD_BF16X6) {
-        delete p;
-        return fail(ETD_EUNSUPPORTED, "the split-BF16 mode-product kernels are not built in this version");
-    }
     *out = p;
     return ETD_OK;
 }
@@ -1189,8 +1278,11 @@ etd_status etd_advance(const etd_plan* plan, void* u, double t0, int nsteps, voi
     if (nsteps == 0) return ETD_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(ws);
-    if (plan->p.prob.precision == ETD_FP64) return advance_t<double>(plan->p, plan->timer, u, t0, nsteps, w, s);
-    return advance_t<float>(plan->p, plan->timer, u, t0, nsteps, w, s);
+    switch (plan->p.prob.precision) {
+    case ETD_FP64: return advance_m<NativeMma<double>>(plan->p, plan->timer, u, t0, nsteps, w, s);
+    case ETD_FP32: return advance_m<NativeMma<float>>(plan->p, plan->timer, u, t0, nsteps, w, s);
+    default: return advance_m<Bf16x6Mma>(plan->p, plan->timer, u, t0, nsteps, w, s);
+    }
 }
 
 etd_status etd_compare(const etd_plan* plan, const void* a, const void* b, double out[4], void* ws, void* stream) {

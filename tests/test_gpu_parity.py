@@ -264,6 +264,46 @@ def test_fp32_fhn2d_against_fp64_oracle(etd, oracle_mod):
 
 
 # ---------------------------------------------------------------------------
+# split-BF16 mode products (six BF16 MFMA terms, FP32 accumulation and state)
+# ---------------------------------------------------------------------------
+
+def test_bf16x6_fisher3d_against_fp64_oracle(etd, oracle_mod):
+    wl = W.fisher3d(n=63, nsteps=200)
+    ref = oracle_mod.advance(wl.problem, wl.u0(), wl.nsteps)
+    got = run_gpu(etd, wl.problem.replace(precision="bf16x6"), wl.u0(), wl.nsteps)
+    err = rel_l2(got, ref)
+    print(f"  bf16x6 rel_l2 vs fp64 oracle = {err:.3e}")
+    assert err <= REDUCED_TOL
+
+
+def test_bf16x6_fisher3d_n255_steps(etd, oracle_mod):
+    """The benchmark workload at full size, 3 steps."""
+    wl = W.fisher3d()
+    ref = oracle_mod.advance(wl.problem, wl.u0(), 3)
+    got = run_gpu(etd, wl.problem.replace(precision="bf16x6"), wl.u0(), 3)
+    err = rel_l2(got, ref)
+    print(f"  bf16x6 rel_l2 vs fp64 oracle = {err:.3e}")
+    assert err <= REDUCED_TOL
+
+
+@pytest.mark.parametrize("dim,n,rxn", [(2, (70, 41), "fisher"), (3, (24, 40, 19), "allen_cahn"),
+                                       (2, (300, 520), "fhn_cubic"), (3, (33, 64, 96), "fhn_classic"),
+                                       (2, (1023, 40), "fisher"), (2, (63, 63), "ac_mms")])
+def test_bf16x6_shapes_and_reactions(etd, oracle_mod, dim, n, rxn):
+    kappa = (1e-3, 2e-4) if rxn.startswith("fhn") else (0.05,)
+    p = W.Problem(dim=dim, n=n, kappa=kappa, q=0.2, tau=0.01, reaction=rxn, precision="bf16x6")
+    if rxn.startswith("fhn"):
+        u0 = W.u0_fhn_patch(p, seed=3, patch=0.3)
+    else:
+        u0 = 0.9 * W.sine_product(p)[None] + 0.05 * W.u0_random(p, seed=4, lo=0, hi=1)
+    ref = oracle_mod.advance(p.replace(precision="fp64"), u0, 20)
+    got = run_gpu(etd, p, u0, 20)
+    err = rel_l2(got, ref)
+    print(f"  bf16x6 rel_l2 vs fp64 oracle = {err:.3e}")
+    assert err <= REDUCED_TOL
+
+
+# ---------------------------------------------------------------------------
 # repeatability, resume, no-op, validation reductions
 # ---------------------------------------------------------------------------
 

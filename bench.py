@@ -10,12 +10,15 @@ in FP64; the reduced-precision variant is timed beside it and its relative L2
 distance to the FP64 result is reported.
 
 Prints one JSON line.  Options: --steps K (timed steps), --warmup W,
---precision fp64|fp32, --reduced fp32|none, --cpu-steps S (oracle sample),
+--precision fp64|fp32|bf16x6, --reduced fp32,bf16x6|none, --cpu-steps S
+(oracle sample),
 --no-cpu-baseline, --n (grid size per direction).
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -23,7 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "grid-point updates/sec (m^d x steps) at 3D m=255, FP64 vs reduced at <=1e-6"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+# dense matrix-core peaks (MI355X datasheet); split-BF16 products are priced
+# at the BF16 rate, six MFMA terms per product
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x6": 2500.0 / 6}
 STAGE_NAMES = ("z_stage", "y_stage", "x_stage")
 # mode products per launch of each stage kind (3-D): z and y apply Q1 to two
 # fields (forward + back each), the fused x stage does five products
@@ -35,8 +40,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--reduced", default="fp32", choices=["fp32", "none"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x6"])
+    ap.add_argument("--reduced", default="fp32,bf16x6",
+                    help="comma-separated reduced-precision variants timed beside fp64, or 'none'")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=255)
@@ -67,6 +73,33 @@ def timed_run(etd, torch, wl, precision, steps, warmup):
     return u, t1 - t0, ms, counts
 
 
+KERNEL_SOURCES = ("paper_2601_06849_amd/csrc/etdds.hip", "paper_2601_06849_amd/csrc/plan.hpp",
+                  "paper_2601_06849_amd/csrc/plan.cpp")
+
+
+def source_fingerprint():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, precision, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (copy-calibrated), or None when there is none or the
+    kernel sources changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    fp = re.search(r"source_sha256: ([0-9a-f]{64})", text)
+    tb = re.search(rf"traffic_bytes_per_launch {kernel}: (\d+)", text)
+    if not fp or not tb or fp.group(1) != source_fingerprint():
+        return None
+    return int(tb.group(1))
+
+
 def roofline(wl, precision, ms, counts):
     n = wl.problem.n[0]
     per_product = 2.0 * n * n ** 3          # one dense mode product, true (unpadded) n
@@ -81,7 +114,7 @@ def roofline(wl, precision, ms, counts):
     a = stages[dom]["tflops"]
     peak = PEAK_TFLOPS[precision]
     return {"bound": "mfma", "kernel": dom, "achieved": round(a, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(a / peak, 4), "traffic": None}, stages
+            "frac": round(a / peak, 4), "traffic": measured_traffic(wl.name, precision, dom)}, stages
 
 
 def main():
@@ -124,7 +157,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x6": "bf16x6->f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": [args.n] * 3, "kappa": wl.problem.kappa[0], "q": wl.problem.q,
                    "tau": wl.problem.tau, "reaction": "u(1-u)", "precision": args.precision,
@@ -135,12 +168,16 @@ def main():
     }
 
     if args.reduced != "none" and args.precision == "fp64":
-        u_red, sec_r, ms_r, counts_r = timed_run(etd, torch, wl, args.reduced, args.steps, args.warmup)
-        diff = (u_red.double() - u_main).norm() / u_main.norm()
-        roof_r, _ = roofline(wl, args.reduced, ms_r, counts_r)
-        out["reduced"] = {"precision": args.reduced, "value": npts * args.steps / sec_r,
-                          "ms_per_step": 1e3 * sec_r / args.steps, "speedup_vs_fp64": sec / sec_r,
-                          "rel_l2_vs_fp64": float(diff), "roofline": roof_r}
+        # reduced-precision variants over the same steps from the same u0; the
+        # FP64 result they are compared with matches the FP64 oracle to 1e-12
+        out["reduced"] = {}
+        for prec in args.reduced.split(","):
+            u_red, sec_r, ms_r, counts_r = timed_run(etd, torch, wl, prec, args.steps, args.warmup)
+            diff = (u_red.double() - u_main).norm() / u_main.norm()
+            roof_r, _ = roofline(wl, prec, ms_r, counts_r)
+            out["reduced"][prec] = {"value": npts * args.steps / sec_r, "ms_per_step": 1e3 * sec_r / args.steps,
+                                    "speedup_vs_fp64": sec / sec_r, "rel_l2_vs_fp64": float(diff),
+                                    "roofline": roof_r}
 
     if not args.no_cpu_baseline:
         import oracle

@@ -129,6 +129,7 @@ template <typename T>
 struct NativeMma {
     typedef T elem;
     static constexpr int KB = 16, KL = 4, NSUB = 4;
+    static constexpr bool SPLIT_B = false;
     typedef vec_t<T, 4> A;
     typedef vec_t<T, 4> B;
     __device__ static A load_a(const void* P, int, long off) {
@@ -149,6 +150,7 @@ struct NativeMma {
 struct Bf16x6Mma {
     typedef float elem;
     static constexpr int KB = 32, KL = 8, NSUB = 6;
+    static constexpr bool SPLIT_B = true;
     struct A {
         bf16x8 p[3];   // hi, mid, lo
     };
@@ -264,15 +266,27 @@ __device__ __forceinline__ void gemm(const void* __restrict__ P, int NP, int rb0
         typename M::A a_nxt[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) a_nxt[r] = M::load_a(P, NP, off[r] + kn);
-        typename M::B b[NQ];
+        if constexpr (M::SPLIT_B) {
+            // split B fragments one at a time (each expands to three pieces)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) b[q] = M::prep(bload(q, kb * M::KB + M::KL * lg));
+            for (int q = 0; q < NQ; ++q) {
+                const typename M::B b = M::prep(bload(q, kb * M::KB + M::KL * lg));
 #pragma unroll
-        for (int t = 0; t < M::NSUB; ++t)
+                for (int t = 0; t < M::NSUB; ++t)
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
+                    for (int r = 0; r < RB; ++r) M::step(acc[r][q], a_cur[r], b, t);
+            }
+        } else {
+            typename M::B b[NQ];
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) M::step(acc[r][q], a_cur[r], b[q], t);
+            for (int q = 0; q < NQ; ++q) b[q] = M::prep(bload(q, kb * M::KB + M::KL * lg));
+#pragma unroll
+            for (int t = 0; t < M::NSUB; ++t)
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) M::step(acc[r][q], a_cur[r], b[q], t);
+        }
 #pragma unroll
         for (int r = 0; r < RB; ++r) a_cur[r] = a_nxt[r];
     }
@@ -336,30 +350,33 @@ __device__ __forceinline__ T react_coupled(const RxnArgs& r, int comp, T mine, T
 
 // Workgroup: NP/(16 RB) waves over one tile of 16*CB columns; wave w owns
 // output row blocks RB*w .. RB*w+RB-1 for all CB column blocks (each P
-// fragment feeds 2*NC*CB MFMAs).  LDS: [2*NC arrays][NP rows][16*CB] of T,
-// first the inputs (and f of them), then the scaled spectral coefficients.
+// fragment feeds 2*NC*CB MFMAs).  LDS: [2*NC arrays][16*CB columns][NP + pad]
+// of T (the contracted index contiguous, so a lane's B fragment is one
+// vector read), first the inputs (and f of them), then the scaled spectral
+// coefficients.
 template <typename M, int NC, bool FIRST, int RB, int CB, int MAXT>
 __global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
-    constexpr int RS = 16 * CB;           // columns per tile
-    constexpr int VPR = RS / VN;          // 16-byte vectors per tile row
+    constexpr int NCOL = 16 * CB;         // columns per tile
+    constexpr int VPR = NCOL / VN;        // 16-byte global vectors per tile row
     constexpr int NA = 2 * NC;
     constexpr int NQ = NA * CB;           // B fragments per K block
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* X = reinterpret_cast<T*>(smem_raw);
 
     const int NP = a.NP;
-    const int AST = NP * RS;
+    const int RS = NP + kInnerRowPad;     // LDS stride between columns
+    const int AST = NCOL * RS;
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
     const int cb = blockIdx.x % a.ncb;
     const long bt = blockIdx.x / a.ncb;
-    const long gbase = bt * a.sb + long(cb) * RS;
+    const long gbase = bt * a.sb + long(cb) * NCOL;
     const T* __restrict__ in0 = static_cast<const T*>(a.in0);
     const T* __restrict__ in1 = static_cast<const T*>(a.in1);
     const void* __restrict__ P = a.P;
@@ -378,7 +395,7 @@ __global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
 #pragma unroll
             for (int t = 0; t < VN; ++t) {
                 int x, y, z;
-                const int col = cb * RS + j0 + t;
+                const int col = cb * NCOL + j0 + t;
                 if (a.dim == 3) {
                     z = k;
                     y = col / a.npx;
@@ -397,16 +414,22 @@ __global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
                 for (int c = 0; c < NC; ++c) f[c][t] = ff[c];
             }
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                *reinterpret_cast<TV*>(X + c * AST + k * RS + j0) = u[c];
-                *reinterpret_cast<TV*>(X + (NC + c) * AST + k * RS + j0) = f[c];
-            }
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int t = 0; t < VN; ++t) {
+                    X[c * AST + (j0 + t) * RS + k] = u[c][t];
+                    X[(NC + c) * AST + (j0 + t) * RS + k] = f[c][t];
+                }
         } else {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                *reinterpret_cast<TV*>(X + c * AST + k * RS + j0) = *reinterpret_cast<const TV*>(in0 + gi + c * a.sc);
-                *reinterpret_cast<TV*>(X + (NC + c) * AST + k * RS + j0) =
-                    *reinterpret_cast<const TV*>(in1 + gi + c * a.sc);
+                const TV g0 = *reinterpret_cast<const TV*>(in0 + gi + c * a.sc);
+                const TV g1 = *reinterpret_cast<const TV*>(in1 + gi + c * a.sc);
+#pragma unroll
+                for (int t = 0; t < VN; ++t) {
+                    X[c * AST + (j0 + t) * RS + k] = g0[t];
+                    X[(NC + c) * AST + (j0 + t) * RS + k] = g1[t];
+                }
             }
         }
     }
@@ -415,15 +438,11 @@ __global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
     const int rb0 = RB * w;
     // fragment qq = array (qq / CB), column block (qq % CB)
     auto bfrag = [&](int qq, int k0) {
-        const T* src = X + (qq / CB) * AST + (qq % CB) * 16 + li;
-        vec_t<T, M::KL> b;
-#pragma unroll
-        for (int e = 0; e < M::KL; ++e) b[e] = src[(k0 + e) * RS];
-        return b;
+        return lds_vec<T, M::KL>(X + (qq / CB) * AST + ((qq % CB) * 16 + li) * RS + k0);
     };
     // element (row of accumulator register e of block rb0+r, column li of block qq%CB) of array qq/CB
     auto at = [&](int qq, int r, int e) -> T& {
-        return X[(qq / CB) * AST + (16 * (rb0 + r) + M::row(lg, e)) * RS + (qq % CB) * 16 + li];
+        return X[(qq / CB) * AST + ((qq % CB) * 16 + li) * RS + 16 * (rb0 + r) + M::row(lg, e)];
     };
     T4 acc[RB][NQ];
     T4 res[RB][NQ];
@@ -1083,6 +1102,11 @@ etd_status launch_x(const XArgs& a, long nlines, typename M::elem* scratch, hipS
         }
         return ETD_OK;
     }
+    // FP32 state: 64-line tiles when the LDS and the line count allow (four
+    // blocks per P fragment; the 16-cycle BF16 steps need it most)
+    if constexpr (sizeof(T) == 4 && NC == 1)
+        if (a.NP <= 256 && nlines % 64 == 0 && x_lds_bytes(a.NP, 2 * NC, 4, sizeof(T)) <= kMaxLds)
+            return launch_x_k<M, NC, 2, 4, 512>(a, nlines, s);
     if (wide_tiles<T, NC>() && a.NP <= 256 && x_lds_bytes(a.NP, 2 * NC, 2, sizeof(T)) <= kMaxLds)
         return launch_x_k<M, NC, 2, 2, 512>(a, nlines, s);
     return DISPATCH_SHAPE(a.NP, X_K, M, NC, 1, a, nlines, s);

@@ -23,10 +23,11 @@ constexpr int kMaxWaves = 16;
 // Row padding (elements) of the x-stage LDS tiles, against bank conflicts.
 constexpr int kInnerRowPad = 4;
 
-// LDS footprint of an outer-stage tile (`arrays` fields of NP rows x 16*cb
-// columns) and of an x-stage tile (`arrays` fields of 16*cb lines x NP).
+// LDS footprint of an outer-stage tile (`arrays` fields of 16*cb columns,
+// each a run of NP contracted indices plus padding) and of an x-stage tile
+// (`arrays` fields of 16*cb lines x NP, plus padding).
 inline size_t outer_lds_bytes(int NP, int arrays, int cb, size_t elem) {
-    return size_t(arrays) * NP * 16 * cb * elem;
+    return size_t(arrays) * 16 * cb * (NP + kInnerRowPad) * elem;
 }
 inline size_t x_lds_bytes(int NP, int arrays, int cb, size_t elem) {
     return size_t(arrays) * 16 * cb * (NP + kInnerRowPad) * elem;

@@ -121,6 +121,25 @@ etd_status etd_compare(const etd_plan* plan, const void* a_dev, const void* b_de
  * of out in doubles; ETD_EINVAL if too small. */
 etd_status etd_plan_table(const etd_plan* plan, int which, int d, int comp, double* out, size_t count);
 
+/* Adjoint of etd_advance (reverse mode), for the gradient of a scalar loss
+ * L(U_N), U_N the field after nsteps steps from u0_dev at time t0.  Given
+ * ubar_final_dev = dL/dU_N (device, field layout), writes dL/du0 to ubar0_dev
+ * and, on the host, grad[c] = dL/dkappa_c for c < ncomp and grad[ncomp] =
+ * dL/dq.  Each stage's transpose is applied in reverse order (the step of
+ * Sec. 3.1 with symmetric, commuting directional operators; the reaction
+ * enters through its pointwise Jacobian); parameter derivatives use
+ * dQ_l(tau lambda)/dlambda and dlambda/dkappa, dlambda/dq.  Forward states are
+ * recomputed from ceil(sqrt(nsteps)) checkpoints held in the adjoint
+ * workspace (etd_adjoint_workspace_bytes bytes, 256-byte aligned, caller-owned);
+ * the plan's workspace is used as scratch.  Synchronises `stream`.  Gradients
+ * are summed in FP64 in a fixed order.  ETD_EUNSUPPORTED when the adjoint's
+ * tiles exceed the on-chip limits (its x tile holds eight fields per
+ * component). */
+etd_status etd_adjoint_workspace_bytes(const etd_plan* plan, int nsteps, size_t* bytes);
+etd_status etd_adjoint(const etd_plan* plan, const void* u0_dev, double t0, int nsteps, const void* ubar_final_dev,
+                       void* ubar0_dev, double* grad, void* workspace_dev, void* adjoint_workspace_dev,
+                       size_t adjoint_bytes, void* stream);
+
 /* Stage timing (diagnostics).  While enabled, etd_advance records a HIP event
  * on its stream before and after every stage kernel.  etd_timing_read waits
  * for the last recorded event and returns, per stage kind (0 = first outer

@@ -51,8 +51,8 @@ class etd_problem(ctypes.Structure):
 _lib = None
 
 EXPORTS = ("etd_plan_create", "etd_plan_workspace_bytes", "etd_plan_upload", "etd_advance", "etd_compare",
-           "etd_plan_table", "etd_timing_enable", "etd_timing_read", "etd_plan_destroy", "etd_status_string",
-           "etd_last_error")
+           "etd_plan_table", "etd_timing_enable", "etd_timing_read", "etd_adjoint_workspace_bytes", "etd_adjoint",
+           "etd_plan_destroy", "etd_status_string", "etd_last_error")
 
 
 def lib():
@@ -71,12 +71,14 @@ def lib():
         L.etd_plan_table.argtypes = [vp, ip, ip, ip, dp, sz]
         L.etd_timing_enable.argtypes = [vp, ip]
         L.etd_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
+        L.etd_adjoint_workspace_bytes.argtypes = [vp, ip, ctypes.POINTER(sz)]
+        L.etd_adjoint.argtypes = [vp, vp, ctypes.c_double, ip, vp, vp, dp, vp, vp, sz, vp]
         L.etd_plan_destroy.argtypes = [vp]
         L.etd_status_string.argtypes = [ip]
         L.etd_status_string.restype = ctypes.c_char_p
         L.etd_last_error.argtypes = []
         L.etd_last_error.restype = ctypes.c_char_p
-        for name in EXPORTS[:9]:
+        for name in EXPORTS[:11]:
             getattr(L, name).restype = ip
         _lib = L
     return _lib
@@ -176,6 +178,22 @@ def etd_timing_read(plan):
     return list(ms), list(cnt)
 
 
+def etd_adjoint_workspace_bytes(plan, nsteps: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().etd_adjoint_workspace_bytes(plan, int(nsteps), ctypes.byref(n)))
+    return int(n.value)
+
+
+def etd_adjoint(plan, u0, t0: float, nsteps: int, ubar_final, ubar0, workspace, adjoint_workspace, ncomp: int,
+                stream=None):
+    """Returns [dL/dkappa_0, ..., dL/dkappa_{ncomp-1}, dL/dq]; writes dL/du0 into ubar0."""
+    grad = (ctypes.c_double * (ncomp + 1))()
+    nbytes = adjoint_workspace.numel() * adjoint_workspace.element_size()
+    _check(lib().etd_adjoint(plan, _ptr(u0), float(t0), int(nsteps), _ptr(ubar_final), _ptr(ubar0), grad,
+                             _ptr(workspace), _ptr(adjoint_workspace), nbytes, _stream(stream)))
+    return list(grad)
+
+
 def etd_plan_destroy(plan):
     _check(lib().etd_plan_destroy(plan))
 
@@ -221,6 +239,18 @@ class Stepper:
     def compare(self, a, b, allow_nonfinite=False):
         return etd_compare(self.plan, a, b, self.workspace, self.stream, allow_nonfinite)
 
+    def adjoint(self, u0, ubar_final, nsteps: int, t0: float = 0.0):
+        """(dL/du0, [dL/dkappa_c..., dL/dq]) for dL/dU_N = ubar_final."""
+        import torch
+        nbytes = etd_adjoint_workspace_bytes(self.plan, nsteps)
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        aws = raw[off:off + nbytes]
+        ubar0 = torch.empty_like(u0)
+        grad = etd_adjoint(self.plan, u0.contiguous(), t0, nsteps, ubar_final.contiguous(), ubar0, self.workspace,
+                           aws, self.problem.ncomp, self.stream)
+        return ubar0, grad
+
     def close(self):
         if self.plan is not None:
             etd_plan_destroy(self.plan)
@@ -231,3 +261,45 @@ class Stepper:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------
+# autograd: U_N = advance(u0; kappa, q) with the hand-written adjoint
+# --------------------------------------------------------------------------
+
+def _autograd():
+    import torch
+
+    class EtdAdvance(torch.autograd.Function):
+        """U_N after nsteps steps from u0; differentiable in u0, kappa and q
+        through etd_adjoint (sqrt(N) checkpointing)."""
+
+        @staticmethod
+        def forward(ctx, u0, kappa, q, problem, nsteps, t0):
+            p = problem.replace(kappa=tuple(float(k) for k in kappa.detach().cpu().reshape(-1)),
+                                q=float(q.detach().cpu()))
+            st = Stepper(p, device=u0.device)
+            u = u0.detach().clone().contiguous()
+            st.advance(u, nsteps, t0)
+            ctx.save_for_backward(u0.detach().clone())
+            ctx.stepper, ctx.nsteps, ctx.t0 = st, nsteps, t0
+            ctx.kshape, ctx.kdev, ctx.qdev = kappa.shape, kappa.device, q.device
+            return u
+
+        @staticmethod
+        def backward(ctx, ubar):
+            (u0,) = ctx.saved_tensors
+            st = ctx.stepper
+            ubar0, grad = st.adjoint(u0, ubar.contiguous(), ctx.nsteps, ctx.t0)
+            nc = st.problem.ncomp
+            gk = torch.tensor(grad[:nc], dtype=torch.float64, device=ctx.kdev).reshape(ctx.kshape)
+            gq = torch.tensor(grad[nc], dtype=torch.float64, device=ctx.qdev)
+            return ubar0, gk, gq, None, None, None
+
+    return EtdAdvance
+
+
+def advance_autograd(u0, kappa, q, problem, nsteps: int, t0: float = 0.0):
+    """Differentiable U_N (torch): gradients reach u0, kappa (one entry per
+    component) and q through the hand-written adjoint."""
+    return _autograd().apply(u0, kappa, q, problem, nsteps, t0)

@@ -21,6 +21,7 @@
 // forward product, the Hadamard scaling and the backward product stay on chip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -198,13 +199,20 @@ struct RxnArgs {
     int kind;
     double p[4];
     double ac_rate;        // -lam + kappa * sum_d mu_d + q (AC_MMS)
+    double ac_mu;          // sum_d mu_d, d psi / d kappa per unit ue (AC_MMS)
     double exp_lt;         // e^{-lam t} at the stage's time (AC_MMS)
     const double* sines;   // [3][kMaxPadded] sin(pi (x_i - lo)/L), 0 on the padding
 };
 
-// psi of the manufactured Allen-Cahn problem at node (x, y, z).
+// Exact solution and psi of the manufactured Allen-Cahn problem at node
+// (x, y, z).  psi depends on kappa and q through ac_rate: d psi / d kappa =
+// ac_mu ue, d psi / d q = ue.
+__device__ __forceinline__ double ac_ue(const RxnArgs& r, int x, int y, int z) {
+    return r.exp_lt * r.sines[x] * r.sines[kMaxPadded + y] * r.sines[2 * kMaxPadded + z];
+}
+
 __device__ __forceinline__ double ac_psi(const RxnArgs& r, int x, int y, int z) {
-    const double ue = r.exp_lt * r.sines[x] * r.sines[kMaxPadded + y] * r.sines[2 * kMaxPadded + z];
+    const double ue = ac_ue(r, x, y, z);
     return r.ac_rate * ue - ue * (1.0 - ue * ue);
 }
 
@@ -238,6 +246,46 @@ __device__ __forceinline__ void react(const RxnArgs& r, const T* u, T* f, int x,
         f[0] = react1<T>(r, u[0], x, y, z);
     } else {
         react2<T>(r, u[0], u[1], f[0], f[1]);
+    }
+}
+
+// J(u)^T g: the transposed pointwise Jacobian of the reaction applied to g
+// (the adjoint of a perturbation of u; the forcing of AC_MMS does not depend
+// on u).
+template <typename T, int NC>
+__device__ __forceinline__ void react_jt(const RxnArgs& r, const T* u, const T* g, T* out) {
+    if constexpr (NC == 1) {
+        T d;
+        switch (r.kind) {
+        case ETD_RXN_LINEAR: d = T(r.p[0]); break;
+        case ETD_RXN_FISHER: d = T(r.p[0]) * (T(1) - T(2) * u[0]); break;
+        case ETD_RXN_ALLEN_CAHN:
+        case ETD_RXN_AC_MMS: d = T(1) - T(3) * u[0] * u[0]; break;
+        case ETD_RXN_SATURATING: {
+            const T om = T(1) - u[0];
+            d = T(r.p[0]) / (om * om);
+            break;
+        }
+        default: d = T(0);
+        }
+        out[0] = d * g[0];
+    } else {
+        T fu_u, fu_v, fv_u, fv_v;
+        if (r.kind == ETD_RXN_FHN_CUBIC) {
+            // fu = u(1-u)(u-a) - v, fv = eps (u - gam v)
+            fu_u = (T(-3) * u[0] + T(2) * (T(1) + T(r.p[0]))) * u[0] - T(r.p[0]);
+            fu_v = T(-1);
+            fv_u = T(r.p[1]);
+            fv_v = -T(r.p[1]) * T(r.p[2]);
+        } else {
+            // fu = u - u^3/3 - v, fv = eps (u - alpha v)
+            fu_u = T(1) - u[0] * u[0];
+            fu_v = T(-1);
+            fv_u = T(r.p[0]);
+            fv_v = -T(r.p[0]) * T(r.p[1]);
+        }
+        out[0] = fu_u * g[0] + fv_u * g[1];
+        out[1] = fu_v * g[0] + fv_v * g[1];
     }
 }
 
@@ -507,6 +555,7 @@ struct XArgs {
     int npy;              // padded y extent (line -> (y, z))
     double tau;
     RxnArgs rxn;          // at t_{n+1}
+    void* Wout;           // when set, W is also written there (the adjoint's replay)
 };
 
 // Workgroup: NP/(16 RB) waves over 16*CB consecutive x-lines.  Wave w owns
@@ -615,6 +664,11 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
                 for (int c = 0; c < NC; ++c)
                     Wv[c] = res[r][c * CB + cb][e] + tau * res[r][(NC + c) * CB + cb][e] + acc[r][c * CB + cb][e];
                 react<T, NC>(a.rxn, Wv, F, 16 * (rb0 + r) + M::row(lg, e), ly, lz);
+                if (a.Wout) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        static_cast<T*>(a.Wout)[c * a.sc + line * NP + 16 * (rb0 + r) + M::row(lg, e)] = Wv[c];
+                }
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const T d = F[c] - res[r][(NC + c) * CB + cb][e];
@@ -820,6 +874,444 @@ __global__ __launch_bounds__(MAXT) void x_stage_u(XSplitArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of one step (reverse mode), for the gradient of a loss of U_N with
+// respect to U_0, kappa_c and q.  With every Q symmetric and the directions
+// commuting, the transpose of the step of Sec. 3.1 is
+//   g  = tau Q3x U+bar,           Wbar = U+bar + J(W)^T g,
+//   wbar = Q1x Wbar,              vbar = tau Q2x Wbar - g,
+//   Ubar = L wbar + J(U)^T L vbar,   L = Q1y Q1z (3-D) or Q1y (2-D),
+// and a parameter p enters through d lambda / d p:
+//   dLoss/dp += <Wbar, dQ1x w> + tau <Wbar, dQ2x v> + tau <U+bar, dQ3x d>
+//             + <wbar, dL U> + <vbar, dL f(U)>,     d = f(W) - v,
+// each <a, dQ b> = sum over lines and modes j of (Pa)_j (Pb)_j Q'(tau
+// lambda_j) tau d lambda_j / d p.  The x-direction part and the rest of the
+// step are two fused kernels; each workgroup accumulates its FP64 partial
+// sums [kappa_0 .. kappa_{NC-1}, q] into its own slot (no atomics, so the
+// result is repeatable).
+// ---------------------------------------------------------------------------
+
+struct GradArgs {
+    const double* table;  // derivative weights, [comp][dir][slot][kMaxPadded]
+    double* partial;      // this launch's slots, NC + 1 doubles per workgroup
+    int dir;              // contracted direction 0/1/2
+    double inv_dim;       // d lambda / d q
+};
+
+// Block reduction of the lanes' partial sums; adds them into the slot of this
+// workgroup (one writer per slot per launch).
+template <int NG>
+__device__ __forceinline__ void add_partials(double (&acc)[NG], double* partial) {
+    __shared__ double red[16][NG];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+        double v = acc[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        acc[k] = v;
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NG; ++k) red[w][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < NG) {
+        double t = 0.0;
+        for (int i = 0; i < int(blockDim.x >> 6); ++i) t += red[i][threadIdx.x];
+        partial[long(blockIdx.x) * NG + threadIdx.x] += t;
+    }
+}
+
+struct XAdjArgs {
+    const void* ubar;     // U+bar, all components (stride sc)
+    const void* W;        // forward W
+    const void* w;        // forward w3
+    const void* v;        // forward w4
+    void* wbar;           // out: Q1x Wbar
+    void* vbar;           // out: tau Q2x Wbar - g
+    const void* P;
+    const void* diag;     // slot X1 of component 0
+    long diag_sstride, diag_cstride;
+    int NP;
+    long sc;
+    int npy;
+    double tau;
+    RxnArgs rxn;          // at t_{n+1}
+    GradArgs grad;
+};
+
+// x-direction adjoint over 16 lines.  LDS: 8*NC fields [16 lines][NP + pad]:
+// ubar, w, v, W (staged), S1 = P ubar, Sw = P w, Sv = P v (own rows), and the
+// scaled coefficients; later slots are reused as noted.
+template <typename M, int NC, int RB, int MAXT>
+__global__ __launch_bounds__(MAXT) void x_adjoint(XAdjArgs a) {
+    typedef typename M::elem T;
+    typedef typename Vec4<T>::type T4;
+    typedef typename Vec16<T>::type TV;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int UB = 0, WW = NC, VV = 2 * NC, FW = 3 * NC, S1 = 4 * NC, SW = 5 * NC, SV = 6 * NC, GS = 7 * NC;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* R = reinterpret_cast<T*>(smem_raw);
+    const int NP = a.NP;
+    const int RS = NP + kInnerRowPad;
+    const int AST = 16 * RS;
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int li = lane & 15, lg = lane >> 4;
+    const long line0 = long(blockIdx.x) * 16;
+    const void* __restrict__ P = a.P;
+    const T tau = T(a.tau);
+    const int vpl = NP / VN;
+    const T* src[4] = {static_cast<const T*>(a.ubar), static_cast<const T*>(a.w), static_cast<const T*>(a.v),
+                       static_cast<const T*>(a.W)};
+#pragma unroll 2
+    for (int v = tid; v < 16 * vpl; v += blockDim.x) {
+        const int j = v / vpl, x = (v - j * vpl) * VN;
+        const long gi = line0 * NP + long(v) * VN;
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                *reinterpret_cast<TV*>(R + (f * NC + c) * AST + j * RS + x) =
+                    *reinterpret_cast<const TV*>(src[f] + c * a.sc + gi);
+    }
+    __syncthreads();
+    const int rb0 = RB * w;
+    auto bfrag_from = [&](int q0) {
+        return [&, q0](int q, int k0) { return lds_vec<T, M::KL>(R + (q0 + q) * AST + li * RS + k0); };
+    };
+    auto at = [&](int q, int r, int e) -> T& { return R[q * AST + li * RS + 16 * (rb0 + r) + M::row(lg, e)]; };
+    const T* __restrict__ dg = static_cast<const T*>(a.diag);
+    const double* gt = a.grad.table;
+    const long gcs = 3L * kGradSlots * kMaxPadded;   // component stride of the weight table
+
+    // ---- S1 = P ubar, Sw = P w, Sv = P v ----
+    T4 ub[RB][NC];
+    {
+        T4 acc[RB][3 * NC];
+        zero<T, RB, 3 * NC>(acc);
+        gemm<M, RB, 3 * NC>(P, NP, rb0, li, lg, acc, bfrag_from(0));
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const T* d3 = dg + c * a.diag_cstride + 2 * a.diag_sstride + 16 * (rb0 + r);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    ub[r][c][e] = at(UB + c, r, e);
+                    at(S1 + c, r, e) = acc[r][c][e];
+                    at(SW + c, r, e) = acc[r][NC + c][e];
+                    at(SV + c, r, e) = acc[r][2 * NC + c][e];
+                    at(GS + c, r, e) = d3[M::row(lg, e)] * acc[r][c][e];   // (q3 - 1/2) S1
+                }
+            }
+    }
+    __syncthreads();
+
+    // ---- g = tau (ubar/2 + P ((q3 - 1/2) S1)); d = f(W) - v; Wbar = ubar + J(W)^T g ----
+    double gacc[NC + 1];
+#pragma unroll
+    for (int k = 0; k <= NC; ++k) gacc[k] = 0.0;
+    T4 g[RB][NC], wb[RB][NC];
+    {
+        T4 acc[RB][NC];
+        zero<T, RB, NC>(acc);
+        gemm<M, RB, NC>(P, NP, rb0, li, lg, acc, bfrag_from(GS));
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                T Wv[NC], F[NC], gg[NC], jt[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    gg[c] = tau * (T(0.5) * ub[r][c][e] + acc[r][c][e]);
+                    g[r][c][e] = gg[c];
+                    Wv[c] = at(FW + c, r, e);
+                }
+                const long line = line0 + li;
+                const int x = 16 * (rb0 + r) + M::row(lg, e), y = int(line % a.npy), z = int(line / a.npy);
+                react<T, NC>(a.rxn, Wv, F, x, y, z);
+                react_jt<T, NC>(a.rxn, Wv, gg, jt);
+                if (a.rxn.kind == ETD_RXN_AC_MMS) {   // psi(t_{n+1}) depends on kappa and q
+                    const double ue = ac_ue(a.rxn, x, y, z) * double(gg[0]);
+                    gacc[0] += a.rxn.ac_mu * ue;
+                    gacc[NC] += ue;
+                }
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    wb[r][c][e] = ub[r][c][e] + jt[c];
+                    at(UB + c, r, e) = F[c] - at(VV + c, r, e);   // d, over ubar
+                    at(WW + c, r, e) = wb[r][c][e];               // Wbar, over w
+                }
+            }
+    }
+    __syncthreads();
+
+    // ---- Sd = P d, S2 = P Wbar; gradient terms; scaled coefficients of S2 ----
+    {
+        T4 acc[RB][2 * NC];
+        zero<T, RB, 2 * NC>(acc);
+        gemm<M, RB, 2 * NC>(P, NP, rb0, li, lg, acc, bfrag_from(UB));
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const T* d1 = dg + c * a.diag_cstride + 16 * (rb0 + r);
+                const T* d2 = d1 + a.diag_sstride;
+                const double* wt = gt + c * gcs + (long(a.grad.dir) * kGradSlots) * kMaxPadded + 16 * (rb0 + r);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = M::row(lg, e);
+                    const double sd = acc[r][c][e], s2 = acc[r][NC + c][e];
+                    const double t = s2 * double(at(SW + c, r, e)) * wt[kGradRho1 * kMaxPadded + k] +
+                                     s2 * double(at(SV + c, r, e)) * wt[kGradRho2 * kMaxPadded + k] +
+                                     double(at(S1 + c, r, e)) * sd * wt[kGradRho3 * kMaxPadded + k];
+                    gacc[c] += t * wt[kGradMu * kMaxPadded + k];
+                    gacc[NC] += t * a.grad.inv_dim;
+                    at(VV + c, r, e) = d1[k] * T(s2);   // (q1 - 1) S2, over v
+                    at(FW + c, r, e) = d2[k] * T(s2);   // tau (q2 - 1) S2, over W
+                }
+            }
+    }
+    __syncthreads();
+
+    // ---- wbar = Wbar + P ((q1 - 1) S2); vbar = -g + tau Wbar + P (tau (q2 - 1) S2) ----
+    {
+        T4 acc[RB][2 * NC];
+        zero<T, RB, 2 * NC>(acc);
+        gemm<M, RB, 2 * NC>(P, NP, rb0, li, lg, acc, bfrag_from(VV));
+        T* __restrict__ ow = static_cast<T*>(a.wbar);
+        T* __restrict__ ov = static_cast<T*>(a.vbar);
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const long o = c * a.sc + (line0 + li) * NP + 16 * (rb0 + r);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int x = M::row(lg, e);
+                    ow[o + x] = wb[r][c][e] + acc[r][c][e];
+                    ov[o + x] = -g[r][c][e] + tau * wb[r][c][e] + acc[r][NC + c][e];
+                }
+            }
+    }
+    __syncthreads();
+    add_partials<NC + 1>(gacc, a.grad.partial);
+}
+
+struct OuterAdjArgs {
+    const void* a0;       // adjoint inputs (two fields)
+    const void* a1;
+    const void* f0;       // forward partners: middle: w1, v1; first: U (f(U) formed here)
+    const void* f1;
+    void* out0;           // Q1 a0, Q1 a1
+    void* out1;
+    const void* P;
+    const void* diag;     // q1 - 1 of this direction, component 0
+    long diag_cstride;
+    int NP, ncb;
+    long sk, sb, sc;
+    int npx, npy, dim;
+    RxnArgs rxn;          // first: f at t_n
+    GradArgs grad;
+};
+
+// Adjoint of an outer stage (z or y): the forward stage applied to the two
+// adjoint fields, plus the gradient terms <a, dQ1 f> against the forward
+// partners.  LDS: 4*NC fields [16 columns][NP + pad]: a0, a1, f0, f1.
+template <typename M, int NC, bool FIRST, int RB, int MAXT>
+__global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
+    typedef typename M::elem T;
+    typedef typename Vec4<T>::type T4;
+    typedef typename Vec16<T>::type TV;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int VPR = 16 / VN;
+    constexpr int NA = 2 * NC, NF = 4 * NC;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* X = reinterpret_cast<T*>(smem_raw);
+    const int NP = a.NP;
+    const int RS = NP + kInnerRowPad;
+    const int AST = 16 * RS;
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int li = lane & 15, lg = lane >> 4;
+    const int cb = blockIdx.x % a.ncb;
+    const long bt = blockIdx.x / a.ncb;
+    const long gbase = bt * a.sb + long(cb) * 16;
+    const void* __restrict__ P = a.P;
+    const T* a0 = static_cast<const T*>(a.a0);
+    const T* a1 = static_cast<const T*>(a.a1);
+    const T* f0 = static_cast<const T*>(a.f0);
+    const T* f1 = static_cast<const T*>(a.f1);
+#pragma unroll 2
+    for (int v = tid; v < NP * VPR; v += blockDim.x) {
+        const int k = v / VPR, j0 = (v - k * VPR) * VN;
+        const long gi = gbase + long(k) * a.sk + j0;
+        TV fa[NC], fb[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const TV x0 = *reinterpret_cast<const TV*>(a0 + gi + c * a.sc);
+            const TV x1 = *reinterpret_cast<const TV*>(a1 + gi + c * a.sc);
+            fa[c] = *reinterpret_cast<const TV*>(f0 + gi + c * a.sc);
+            if constexpr (!FIRST) fb[c] = *reinterpret_cast<const TV*>(f1 + gi + c * a.sc);
+#pragma unroll
+            for (int t = 0; t < VN; ++t) {
+                X[c * AST + (j0 + t) * RS + k] = x0[t];
+                X[(NC + c) * AST + (j0 + t) * RS + k] = x1[t];
+            }
+        }
+        if constexpr (FIRST) {
+#pragma unroll
+            for (int t = 0; t < VN; ++t) {
+                const int col = cb * 16 + j0 + t;
+                int x, y, z;
+                if (a.dim == 3) {
+                    z = k;
+                    y = col / a.npx;
+                    x = col - y * a.npx;
+                } else {
+                    z = 0;
+                    y = k;
+                    x = col;
+                }
+                T uu[NC], ff[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) uu[c] = fa[c][t];
+                react<T, NC>(a.rxn, uu, ff, x, y, z);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) fb[c][t] = ff[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int t = 0; t < VN; ++t) {
+                X[(NA + c) * AST + (j0 + t) * RS + k] = fa[c][t];
+                X[(NA + NC + c) * AST + (j0 + t) * RS + k] = fb[c][t];
+            }
+    }
+    __syncthreads();
+    const int rb0 = RB * w;
+    auto bfrag = [&](int q, int k0) { return lds_vec<T, M::KL>(X + q * AST + li * RS + k0); };
+    auto at = [&](int q, int r, int e) -> T& { return X[q * AST + li * RS + 16 * (rb0 + r) + M::row(lg, e)]; };
+    const T* __restrict__ dg = static_cast<const T*>(a.diag);
+    const double* gt = a.grad.table;
+    const long gcs = 3L * kGradSlots * kMaxPadded;
+    double gacc[NC + 1];
+#pragma unroll
+    for (int k = 0; k <= NC; ++k) gacc[k] = 0.0;
+    T4 acc[RB][NF];
+    T4 res[RB][NA];
+    zero<T, RB, NF>(acc);
+    gemm<M, RB, NF>(P, NP, rb0, li, lg, acc, bfrag);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double* wt = gt + c * gcs + (long(a.grad.dir) * kGradSlots) * kMaxPadded + 16 * (rb0 + r);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = M::row(lg, e);
+                const double t = (double(acc[r][c][e]) * acc[r][NA + c][e] +
+                                  double(acc[r][NC + c][e]) * acc[r][NA + NC + c][e]) *
+                                 wt[kGradRho1 * kMaxPadded + k];
+                gacc[c] += t * wt[kGradMu * kMaxPadded + k];
+                gacc[NC] += t * a.grad.inv_dim;
+            }
+        }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < NA; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) res[r][q][e] = at(q, r, e);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const T* dc = dg + (q % NC) * a.diag_cstride + 16 * (rb0 + r);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) at(q, r, e) = acc[r][q][e] * dc[M::row(lg, e)];
+        }
+    __syncthreads();
+    T4 acc2[RB][NA];
+    zero<T, RB, NA>(acc2);
+    gemm<M, RB, NA>(P, NP, rb0, li, lg, acc2, bfrag);
+    T* __restrict__ out0 = static_cast<T*>(a.out0);
+    T* __restrict__ out1 = static_cast<T*>(a.out1);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            T* o = (q < NC ? out0 : out1) + (q % NC) * a.sc + gbase + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[long(16 * (rb0 + r) + M::row(lg, e)) * a.sk] = res[r][q][e] + acc2[r][q][e];
+        }
+    __syncthreads();
+    add_partials<NC + 1>(gacc, a.grad.partial);
+}
+
+// Ubar = A + J(U)^T B over a padded field (all components at each node).
+// B is the adjoint of f(t_n, U); where f depends on kappa or q explicitly
+// (AC_MMS) the block adds <B, d f / d p> to its gradient slot.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void add_jt_field(const T* __restrict__ U, const T* __restrict__ A,
+                                                    const T* __restrict__ B, T* __restrict__ out, long npts,
+                                                    RxnArgs r, int px, int py, double* partial) {
+    if (r.kind == ETD_RXN_AC_MMS) {
+        double gacc[NC + 1];
+#pragma unroll
+        for (int k = 0; k <= NC; ++k) gacc[k] = 0.0;
+        for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < npts; i += long(gridDim.x) * blockDim.x) {
+            const long yz = i / px;
+            const double ue = ac_ue(r, int(i - yz * px), int(yz % py), int(yz / py)) * double(B[i]);
+            gacc[0] += r.ac_mu * ue;
+            gacc[NC] += ue;
+        }
+        add_partials<NC + 1>(gacc, partial);
+    }
+    for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < npts; i += long(gridDim.x) * blockDim.x) {
+        T u[NC], b[NC], jt[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            u[c] = U[c * npts + i];
+            b[c] = B[c * npts + i];
+        }
+        react_jt<T, NC>(r, u, b, jt);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[c * npts + i] = A[c * npts + i] + jt[c];
+    }
+}
+
+template <typename T>
+__global__ void copy_field(const T* __restrict__ src, T* __restrict__ dst, long n) {
+    for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < n; i += long(gridDim.x) * blockDim.x) dst[i] = src[i];
+}
+
+__global__ void fill_zero(double* __restrict__ p, long n) {
+    for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < n; i += long(gridDim.x) * blockDim.x) p[i] = 0.0;
+}
+
+// Sum the workgroup slots (fixed order) into out[NG].
+__global__ void sum_partials(const double* __restrict__ part, long nslots, int ng, double* __restrict__ out) {
+    __shared__ double sh[256];
+    for (int k = 0; k < ng; ++k) {
+        double t = 0.0;
+        for (long i = threadIdx.x; i < nslots; i += blockDim.x) t += part[i * ng + k];
+        sh[threadIdx.x] = t;
+        __syncthreads();
+        for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+            if (int(threadIdx.x) < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = sh[0];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Layout conversion and validation reductions
 // ---------------------------------------------------------------------------
 
@@ -945,6 +1437,7 @@ RxnArgs rxn_args(const Plan& pl, const char* ws, double t) {
     for (int i = 0; i < 4; ++i) r.p[i] = p.rxn_param[i];
     r.sines = reinterpret_cast<const double*>(ws + pl.lay.sines);
     r.ac_rate = 0.0;
+    r.ac_mu = 0.0;
     r.exp_lt = 0.0;
     if (p.rxn == ETD_RXN_AC_MMS) {
         const double lam = p.rxn_param[0];
@@ -960,6 +1453,7 @@ RxnArgs rxn_args(const Plan& pl, const char* ws, double t) {
             }
         }
         r.ac_rate = -lam + p.kappa[0] * mu + p.q;
+        r.ac_mu = mu;
         r.exp_lt = std::exp(-lam * t);
     }
     return r;
@@ -1125,7 +1619,8 @@ etd_status timer_mark(StageTimer& t, int kind, bool begin, hipStream_t s);
     } while (0)
 
 template <typename M, int NC>
-etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int nsteps, hipStream_t s) {
+etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int nsteps, hipStream_t s,
+                     typename M::elem* w_out = nullptr) {
     typedef typename M::elem T;
     const int px = pl.np[0], py = pl.np[1], pz = pl.np[2];
     const long sc = long(px) * py * pz;
@@ -1206,6 +1701,7 @@ etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int ns
         x.npy = py;
         x.tau = tau;
         x.rxn = rxn_args(pl, ws, tn1);
+        x.Wout = w_out;
         TIMED(2, (launch_x<M, NC>(x, long(py) * pz, pl.dim == 3 ? WA : WC, s)));
     }
     return ETD_OK;
@@ -1222,6 +1718,249 @@ etd_status advance_m(const Plan& pl, StageTimer& tm, void* u, double t0, int nst
     if (st != ETD_OK) return st;
     hipLaunchKernelGGL(unpack_field<T>, dim3(2048), dim3(256), 0, s, U, static_cast<T*>(u), d);
     HIP_TRY(hipGetLastError(), "unpack launch");
+    return ETD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint driver: sqrt(N) checkpointing
+// ---------------------------------------------------------------------------
+
+struct AdjLayout {
+    int K = 1, nck = 1;          // segment length and number of checkpoints
+    size_t field = 0;            // bytes per padded field
+    size_t ck = 0, seg = 0;      // checkpoint and segment states
+    size_t Wf = 0, Ub = 0, A[4] = {0, 0, 0, 0};
+    // gradient slots of the x, y and z adjoint kernels and of the pointwise kernel
+    size_t part[4] = {0, 0, 0, 0};
+    long nslots[4] = {0, 0, 0, 0};
+    size_t gsum = 0;             // reduced gradient sums [4][NC + 1]
+    size_t total = 0;
+};
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr long kPointSlots = 2048;   // workgroups of the pointwise adjoint kernel
+
+AdjLayout adjoint_layout(const Plan& pl, int nsteps) {
+    AdjLayout L;
+    L.K = std::max(1, int(std::ceil(std::sqrt(double(std::max(nsteps, 1))))));
+    L.nck = (std::max(nsteps, 1) + L.K - 1) / L.K;
+    L.field = pl.lay.field_bytes;
+    const int ng = pl.nc + 1;
+    const int px = pl.np[0], py = pl.np[1], pz = pl.np[2];
+    L.nslots[0] = long(py) * pz / 16;
+    if (pl.dim == 3) {
+        L.nslots[1] = long(px) / 16 * pz;
+        L.nslots[2] = long(px) * py / 16;
+    } else {
+        L.nslots[1] = long(px) / 16;
+    }
+    L.nslots[3] = kPointSlots;
+    size_t off = 0;
+    L.ck = off;
+    off += size_t(L.nck) * L.field;
+    L.seg = off;
+    off += size_t(L.K) * L.field;
+    L.Wf = off;
+    off += L.field;
+    L.Ub = off;
+    off += L.field;
+    for (int i = 0; i < 4; ++i) {
+        L.A[i] = off;
+        off += L.field;
+    }
+    for (int k = 0; k < 4; ++k) {
+        L.part[k] = off;
+        off = a256(off + size_t(std::max(L.nslots[k], 1L)) * ng * 8);
+    }
+    L.gsum = off;
+    off = a256(off + 4 * size_t(ng) * 8);
+    L.total = off;
+    return L;
+}
+
+size_t x_adjoint_lds(int NP, int nc, size_t elem) { return x_lds_bytes(NP, 8 * nc, 1, elem); }
+size_t outer_adjoint_lds(int NP, int nc, size_t elem) { return outer_lds_bytes(NP, 4 * nc, 1, elem); }
+constexpr size_t kStaticLds = 1024;   // the reduction scratch of add_partials
+
+etd_status adjoint_supported(const Plan& pl) {
+    const size_t e = pl.elem;
+    if (!x_fused(pl.np[0], pl.nc, e) || x_adjoint_lds(pl.np[0], pl.nc, e) + kStaticLds > kMaxLds)
+        return fail(ETD_EUNSUPPORTED, "the adjoint x tile exceeds the LDS budget at this size, precision and component count");
+    for (int d = 1; d < pl.dim; ++d)
+        if (outer_adjoint_lds(pl.np[d], pl.nc, e) + kStaticLds > kMaxLds)
+            return fail(ETD_EUNSUPPORTED, "the adjoint outer tile exceeds the LDS budget at this size and precision");
+    return ETD_OK;
+}
+
+template <typename M, int NC, int RB, int MAXT>
+etd_status launch_xadj_k(const XAdjArgs& a, long nlines, hipStream_t s) {
+    typedef typename M::elem T;
+    const size_t lds = x_adjoint_lds(a.NP, NC, sizeof(T));
+    auto k = x_adjoint<M, NC, RB, MAXT>;
+    static size_t done = 0;
+    HIP_TRY(set_lds(k, lds, done), "adjoint x LDS attribute");
+    hipLaunchKernelGGL(k, dim3(unsigned(nlines / 16)), dim3(tile_threads(a.NP)), lds, s, a);
+    HIP_TRY(hipGetLastError(), "adjoint x launch");
+    return ETD_OK;
+}
+#define XADJ_K(RB, MAXT, M, NC, a, nl, s) launch_xadj_k<M, NC, RB, MAXT>(a, nl, s)
+
+template <typename M, int NC, bool FIRST, int RB, int MAXT>
+etd_status launch_oadj_k(const OuterAdjArgs& a, long nblocks, hipStream_t s) {
+    typedef typename M::elem T;
+    const size_t lds = outer_adjoint_lds(a.NP, NC, sizeof(T));
+    auto k = outer_adjoint<M, NC, FIRST, RB, MAXT>;
+    static size_t done = 0;
+    HIP_TRY(set_lds(k, lds, done), "adjoint outer LDS attribute");
+    hipLaunchKernelGGL(k, dim3(unsigned(nblocks)), dim3(tile_threads(a.NP)), lds, s, a);
+    HIP_TRY(hipGetLastError(), "adjoint outer launch");
+    return ETD_OK;
+}
+#define OADJ_K(RB, MAXT, M, NC, FIRST, a, nb, s) launch_oadj_k<M, NC, FIRST, RB, MAXT>(a, nb, s)
+
+template <typename T>
+etd_status copy_f(const T* src, T* dst, long n, hipStream_t s) {
+    hipLaunchKernelGGL(copy_field<T>, dim3(2048), dim3(256), 0, s, src, dst, n);
+    HIP_TRY(hipGetLastError(), "copy launch");
+    return ETD_OK;
+}
+
+#define TRY(expr)                          \
+    do {                                   \
+        const etd_status st_ = (expr);     \
+        if (st_ != ETD_OK) return st_;     \
+    } while (0)
+
+template <typename M, int NC>
+etd_status adjoint_t(const Plan& pl, StageTimer& tm, const void* u0, double t0, int N, const void* ubarN,
+                     void* ubar0, double* grad, char* ws, char* aws, const AdjLayout& L, hipStream_t s) {
+    typedef typename M::elem T;
+    const int px = pl.np[0], py = pl.np[1], pz = pl.np[2];
+    const long sc = long(px) * py * pz;
+    const long nf = sc * NC;   // elements per field
+    const double tau = pl.prob.tau;
+    const Dims dm = dims_of(pl);
+    const int ng = NC + 1;
+    auto F = [&](size_t off) { return reinterpret_cast<T*>(aws + off); };
+    T* U = reinterpret_cast<T*>(ws + pl.lay.field[0]);
+    T* WA = reinterpret_cast<T*>(ws + pl.lay.field[1]);
+    T* WB = reinterpret_cast<T*>(ws + pl.lay.field[2]);
+    T* WC = reinterpret_cast<T*>(ws + pl.lay.field[3]);
+    T* WD = reinterpret_cast<T*>(ws + pl.lay.field[4]);
+    T* ck = F(L.ck);
+    T* seg = F(L.seg);
+    T* Wf = F(L.Wf);
+    T* Ub = F(L.Ub);
+    T* A[4] = {F(L.A[0]), F(L.A[1]), F(L.A[2]), F(L.A[3])};
+    const size_t fe = L.field / sizeof(T);   // elements between consecutive fields
+    const T* diag = reinterpret_cast<const T*>(ws + pl.lay.diag);
+    const long dstride = long(pl.diag_stride), dcs = long(kDiagSlots) * dstride;
+    const double* gtab = reinterpret_cast<const double*>(ws + pl.lay.grad);
+
+    // ---- forward pass: checkpoints every K steps ----
+    hipLaunchKernelGGL(pack_field<T>, dim3(2048), dim3(256), 0, s, static_cast<const T*>(u0), U, dm);
+    HIP_TRY(hipGetLastError(), "pack launch");
+    for (int c = 0; c < L.nck; ++c) {
+        TRY(copy_f<T>(U, ck + c * fe, nf, s));
+        const int n0 = c * L.K, n1 = std::min(N, n0 + L.K);
+        if (c + 1 < L.nck) TRY((run_steps<M, NC>(pl, tm, ws, t0 + n0 * tau, n1 - n0, s)));
+    }
+    // ---- adjoint state and gradient slots ----
+    hipLaunchKernelGGL(pack_field<T>, dim3(2048), dim3(256), 0, s, static_cast<const T*>(ubarN), Ub, dm);
+    HIP_TRY(hipGetLastError(), "pack launch");
+    for (int k = 0; k < 4; ++k) {
+        hipLaunchKernelGGL(fill_zero, dim3(64), dim3(256), 0, s, reinterpret_cast<double*>(aws + L.part[k]),
+                           std::max(L.nslots[k], 1L) * ng);
+        HIP_TRY(hipGetLastError(), "fill launch");
+    }
+    const double inv_dim = 1.0 / pl.dim;
+
+    for (int c = L.nck - 1; c >= 0; --c) {
+        const int n0 = c * L.K, n1 = std::min(N, n0 + L.K);
+        // replay the segment, keeping every state
+        TRY(copy_f<T>(ck + c * fe, U, nf, s));
+        for (int i = 0; i < n1 - n0; ++i) {
+            TRY(copy_f<T>(U, seg + i * fe, nf, s));
+            if (i + 1 < n1 - n0) TRY((run_steps<M, NC>(pl, tm, ws, t0 + (n0 + i) * tau, 1, s)));
+        }
+        for (int i = n1 - n0 - 1; i >= 0; --i) {
+            const int n = n0 + i;
+            const double tn = t0 + n * tau, tn1 = t0 + (n + 1) * tau;
+            T* Un = seg + i * fe;
+            // regenerate the stage fields of step n (w1, v1 in WA, WB; w, v in WC, WD; W in Wf)
+            TRY(copy_f<T>(Un, U, nf, s));
+            TRY((run_steps<M, NC>(pl, tm, ws, tn, 1, s, Wf)));
+            // x direction
+            XAdjArgs xa{};
+            xa.ubar = Ub;
+            xa.W = Wf;
+            xa.w = pl.dim == 3 ? WC : WA;
+            xa.v = pl.dim == 3 ? WD : WB;
+            xa.wbar = A[0];
+            xa.vbar = A[1];
+            xa.P = ws + pl.lay.P[0];
+            xa.diag = diag + long(kDiagX1) * dstride;
+            xa.diag_sstride = dstride;
+            xa.diag_cstride = dcs;
+            xa.NP = px;
+            xa.sc = sc;
+            xa.npy = py;
+            xa.tau = tau;
+            xa.rxn = rxn_args(pl, ws, tn1);
+            xa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[0]), 0, inv_dim};
+            TRY(DISPATCH_SHAPE(px, XADJ_K, M, NC, xa, long(py) * pz, s));
+            // outer directions
+            OuterAdjArgs oa{};
+            oa.diag_cstride = dcs;
+            oa.sc = sc;
+            oa.npx = px;
+            oa.npy = py;
+            oa.dim = pl.dim;
+            oa.rxn = rxn_args(pl, ws, tn);
+            const T *Lw, *Lv;
+            if (pl.dim == 3) {
+                oa.a0 = A[0]; oa.a1 = A[1]; oa.f0 = WA; oa.f1 = WB; oa.out0 = A[2]; oa.out1 = A[3];
+                oa.P = ws + pl.lay.P[1];
+                oa.diag = diag + long(kDiagY) * dstride;
+                oa.NP = py; oa.ncb = px / 16; oa.sk = px; oa.sb = long(px) * py;
+                oa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[1]), 1, inv_dim};
+                TRY(DISPATCH_SHAPE(py, OADJ_K, M, NC, false, oa, long(px / 16) * pz, s));
+                oa.a0 = A[2]; oa.a1 = A[3]; oa.f0 = Un; oa.f1 = nullptr; oa.out0 = A[0]; oa.out1 = A[1];
+                oa.P = ws + pl.lay.P[2];
+                oa.diag = diag + long(kDiagZ) * dstride;
+                oa.NP = pz; oa.ncb = px * py / 16; oa.sk = long(px) * py; oa.sb = 0;
+                oa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[2]), 2, inv_dim};
+                TRY(DISPATCH_SHAPE(pz, OADJ_K, M, NC, true, oa, long(px) * py / 16, s));
+                Lw = A[0];
+                Lv = A[1];
+            } else {
+                oa.a0 = A[0]; oa.a1 = A[1]; oa.f0 = Un; oa.f1 = nullptr; oa.out0 = A[2]; oa.out1 = A[3];
+                oa.P = ws + pl.lay.P[1];
+                oa.diag = diag + long(kDiagY) * dstride;
+                oa.NP = py; oa.ncb = px / 16; oa.sk = px; oa.sb = 0;
+                oa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[1]), 1, inv_dim};
+                TRY(DISPATCH_SHAPE(py, OADJ_K, M, NC, true, oa, long(px / 16), s));
+                Lw = A[2];
+                Lv = A[3];
+            }
+            hipLaunchKernelGGL((add_jt_field<T, NC>), dim3(unsigned(kPointSlots)), dim3(256), 0, s, Un, Lw, Lv, Ub,
+                               sc, rxn_args(pl, ws, tn), px, py, reinterpret_cast<double*>(aws + L.part[3]));
+            HIP_TRY(hipGetLastError(), "adjoint pointwise launch");
+        }
+    }
+    hipLaunchKernelGGL(unpack_field<T>, dim3(2048), dim3(256), 0, s, Ub, static_cast<T*>(ubar0), dm);
+    HIP_TRY(hipGetLastError(), "unpack launch");
+    double* gs = reinterpret_cast<double*>(aws + L.gsum);
+    for (int k = 0; k < 4; ++k) {
+        hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, s, reinterpret_cast<const double*>(aws + L.part[k]),
+                           std::max(L.nslots[k], 1L), ng, gs + k * ng);
+        HIP_TRY(hipGetLastError(), "gradient reduction launch");
+    }
+    double host[4 * 3];
+    HIP_TRY(hipMemcpyAsync(host, gs, 4 * ng * sizeof(double), hipMemcpyDeviceToHost, s), "gradient copy");
+    HIP_TRY(hipStreamSynchronize(s), "gradient sync");
+    for (int k = 0; k < ng; ++k) grad[k] = host[k] + host[ng + k] + host[2 * ng + k] + host[3 * ng + k];
     return ETD_OK;
 }
 
@@ -1306,6 +2045,45 @@ etd_status etd_advance(const etd_plan* plan, void* u, double t0, int nsteps, voi
     case ETD_FP64: return advance_m<NativeMma<double>>(plan->p, plan->timer, u, t0, nsteps, w, s);
     case ETD_FP32: return advance_m<NativeMma<float>>(plan->p, plan->timer, u, t0, nsteps, w, s);
     default: return advance_m<Bf16x6Mma>(plan->p, plan->timer, u, t0, nsteps, w, s);
+    }
+}
+
+etd_status etd_adjoint_workspace_bytes(const etd_plan* plan, int nsteps, size_t* bytes) {
+    if (!plan || !bytes) return fail(ETD_EINVAL, "NULL argument");
+    if (nsteps < 1) return fail(ETD_EINVAL, "nsteps must be >= 1");
+    const etd_status st = adjoint_supported(plan->p);
+    if (st != ETD_OK) return st;
+    *bytes = adjoint_layout(plan->p, nsteps).total;
+    return ETD_OK;
+}
+
+etd_status etd_adjoint(const etd_plan* plan, const void* u0, double t0, int nsteps, const void* ubar_final,
+                       void* ubar0, double* grad, void* ws, void* adj_ws, size_t adj_bytes, void* stream) {
+    if (!plan || !u0 || !ubar_final || !ubar0 || !grad) return fail(ETD_EINVAL, "NULL argument");
+    if (nsteps < 1) return fail(ETD_EINVAL, "nsteps must be >= 1");
+    if (!std::isfinite(t0)) return fail(ETD_EINVAL, "t0 must be finite");
+    etd_status st = check_ws(plan->p, ws);
+    if (st != ETD_OK) return st;
+    st = adjoint_supported(plan->p);
+    if (st != ETD_OK) return st;
+    const AdjLayout L = adjoint_layout(plan->p, nsteps);
+    if (!adj_ws || reinterpret_cast<uintptr_t>(adj_ws) % 256 != 0)
+        return fail(ETD_EWORKSPACE, "adjoint workspace must be non-NULL and 256-byte aligned");
+    if (adj_bytes < L.total) return fail(ETD_EWORKSPACE, "adjoint workspace smaller than etd_adjoint_workspace_bytes()");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    char* a = static_cast<char*>(adj_ws);
+    const Plan& pl = plan->p;
+    switch (pl.prob.precision) {
+    case ETD_FP64:
+        return pl.nc == 1 ? adjoint_t<NativeMma<double>, 1>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s)
+                          : adjoint_t<NativeMma<double>, 2>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s);
+    case ETD_FP32:
+        return pl.nc == 1 ? adjoint_t<NativeMma<float>, 1>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s)
+                          : adjoint_t<NativeMma<float>, 2>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s);
+    default:
+        return pl.nc == 1 ? adjoint_t<Bf16x6Mma, 1>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s)
+                          : adjoint_t<Bf16x6Mma, 2>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s);
     }
 }
 

@@ -32,6 +32,26 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// Derivatives Q_l'(z) of the rational factors (quotient rule on the
+// polynomial forms below).
+void rational_derivative(int pade, double z, double dq[3]) {
+    if (pade == 4) {
+        const double den = (((z + 4.0) * z + 12.0) * z + 24.0) * z + 24.0;
+        const double dden = ((4.0 * z + 12.0) * z + 24.0) * z + 24.0;
+        const double n2 = ((z + 4.0) * z + 12.0) * z + 24.0, dn2 = (3.0 * z + 8.0) * z + 12.0;
+        const double n3 = ((z + 3.0) * z + 8.0) * z + 12.0, dn3 = (3.0 * z + 6.0) * z + 8.0;
+        const double d2 = den * den;
+        dq[0] = -24.0 * dden / d2;
+        dq[1] = (dn2 * den - n2 * dden) / d2;
+        dq[2] = (dn3 * den - n3 * dden) / d2;
+    } else {
+        const double D = (z + 2.0) * z + 2.0, dD = 2.0 * z + 2.0, D2 = D * D;
+        dq[0] = -2.0 * dD / D2;
+        dq[1] = -((z + 4.0) * z + 2.0) / D2;
+        dq[2] = -(z + 2.0) * z / D2;
+    }
+}
+
 // Rational factors at z = tau*lambda >= 0.  out[0..2] = Q_1..Q_3 and
 // inc[0..2] = Q_1 - 1, Q_2 - 1, Q_3 - 1/2.
 void rational(int pade, double z, double out[3], double inc[3]) {
@@ -184,6 +204,8 @@ etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
     off = align256(off + L.diag_bytes);
     L.sines = off;
     off = align256(off + 3 * size_t(kMaxPadded) * 8);
+    L.grad = off;
+    off = align256(off + size_t(pl.nc) * 3 * kGradSlots * kMaxPadded * 8);
     pl.table_bytes = off;
     L.field_bytes = align256(size_t(pl.nc) * pl.np[0] * pl.np[1] * pl.np[2] * pl.elem);
     for (int f = 0; f < 5; ++f) {
@@ -249,6 +271,21 @@ etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
     }
     if (p.dim == 2)
         for (int i = 0; i < kMaxPadded; ++i) put<double>(pl.image, L.sines, 2 * size_t(kMaxPadded) + i, i == 0 ? 1.0 : 0.0);
+    // Derivative weights of the adjoint (zero on the padding).
+    for (int c = 0; c < pl.nc; ++c)
+        for (int d = 0; d < p.dim; ++d) {
+            const double h = (p.hi[d] - p.lo[d]) / (pl.n[d] + 1);
+            for (int j = 0; j < pl.n[d]; ++j) {
+                double dq[3];
+                rational_derivative(p.pade, p.tau * pl.lam[d][c][j], dq);
+                const double sn = std::sin((j + 1) * M_PI / (2.0 * (pl.n[d] + 1)));
+                const size_t base = ((size_t(c) * 3 + d) * kGradSlots) * kMaxPadded + j;
+                put<double>(pl.image, L.grad, base + kGradRho1 * kMaxPadded, p.tau * dq[0]);
+                put<double>(pl.image, L.grad, base + kGradRho2 * kMaxPadded, p.tau * p.tau * dq[1]);
+                put<double>(pl.image, L.grad, base + kGradRho3 * kMaxPadded, p.tau * p.tau * dq[2]);
+                put<double>(pl.image, L.grad, base + kGradMu * kMaxPadded, 4.0 / (h * h) * sn * sn);
+            }
+        }
     return ETD_OK;
 }
 

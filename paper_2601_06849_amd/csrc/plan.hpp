@@ -46,6 +46,7 @@ struct Layout {
     size_t diag;        // increment-form rational factors, see DiagSlot
     size_t diag_bytes;
     size_t sines;       // FP64 sin(pi (x_i - lo)/L) per direction (AC_MMS forcing)
+    size_t grad;        // FP64 derivative weights of the adjoint, see GradSlot
     size_t field[5];    // padded fields: U, WA, WB, WC, WD
     size_t field_bytes;
     size_t reduce;      // FP64 partial sums of etd_compare
@@ -60,6 +61,17 @@ enum DiagSlot {
     kDiagX2 = 3,  // tau (Q2(tau lambda_x) - 1)
     kDiagX3 = 4,  // Q3(tau lambda_x) - 1/2
     kDiagSlots = 5
+};
+
+// Slots of the FP64 derivative-weight table [component][direction][slot][kMaxPadded]
+// used by the adjoint's parameter gradients: d Q_l(tau lambda)/d lambda times
+// the factor with which Q_l enters the step, and d lambda / d kappa.
+enum GradSlot {
+    kGradRho1 = 0,  // tau Q1'(tau lambda)
+    kGradRho2 = 1,  // tau * tau Q2'(tau lambda)   (x only)
+    kGradRho3 = 2,  // tau * tau Q3'(tau lambda)   (x only)
+    kGradMu = 3,    // d lambda / d kappa = (4/h^2) sin^2(...)
+    kGradSlots = 4
 };
 
 struct Plan {

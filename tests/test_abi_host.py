@@ -177,3 +177,27 @@ def test_host_side_argument_errors_touch_nothing(etd):
         assert etd.etd_status_string(etd.ETD_EWORKSPACE) == "bad workspace"
     finally:
         etd.etd_plan_destroy(plan)
+
+
+def test_adjoint_workspace_query(etd):
+    """The adjoint's x tile holds eight fields per component; FP64 systems fit
+    up to 64 points in x, FP32 systems up to 128."""
+    ok = W.Problem(dim=3, n=(127, 127, 127), kappa=(1e-4, 1e-5), tau=0.02, reaction="fhn_cubic", precision="fp32")
+    plan = etd.etd_plan_create(ok)
+    try:
+        n1 = etd.etd_adjoint_workspace_bytes(plan, 400)
+        n2 = etd.etd_adjoint_workspace_bytes(plan, 100)
+        assert n1 > n2 > 0
+        with pytest.raises(etd.EtdError) as ei:
+            etd.etd_adjoint_workspace_bytes(plan, 0)
+        assert ei.value.status == etd.ETD_EINVAL
+    finally:
+        etd.etd_plan_destroy(plan)
+    big = ok.replace(precision="fp64")
+    plan = etd.etd_plan_create(big)
+    try:
+        with pytest.raises(etd.EtdError) as ei:
+            etd.etd_adjoint_workspace_bytes(plan, 10)
+        assert ei.value.status == etd.ETD_EUNSUPPORTED
+    finally:
+        etd.etd_plan_destroy(plan)

@@ -12,11 +12,14 @@ distance to the FP64 result is reported.
 Prints one JSON line.  Options: --steps K (timed steps), --warmup W,
 --precision fp64|fp32|bf16x6, --reduced fp32,bf16x6|none, --cpu-steps S
 (oracle sample),
---no-cpu-baseline, --n (grid size per direction).
+--no-cpu-baseline, --n (grid size per direction), --adjoint-steps N (the
+adjoint leg: one gradient of 1/2||u(T) - u_target||^2 through N steps of the
+3-D FitzHugh-Nagumo workload, 127^3, FP32; 0 skips it).
 """
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -46,6 +49,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=255)
+    ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     return ap.parse_args()
@@ -117,6 +121,39 @@ def roofline(wl, precision, ms, counts):
             "frac": round(a / peak, 4), "traffic": measured_traffic(wl.name, precision, dom)}, stages
 
 
+def adjoint_leg(etd, torch, W, nsteps):
+    """Time one forward run and one adjoint (gradient w.r.t. u0, kappa, q)
+    over nsteps steps of the 3-D FitzHugh-Nagumo workload; the loss target is
+    u(T) of a run at 1.1 kappa_u."""
+    wl = W.fhn3d(nsteps=nsteps)
+    p = wl.problem
+    st = etd.Stepper(p)
+    u0 = st.field(wl.u0())
+    tp = etd.Stepper(p.replace(kappa=(p.kappa[0] * 1.1, p.kappa[1])))
+    target = tp.advance(u0.clone(), nsteps)
+    tp.close()
+    u = st.advance(u0.clone(), 2)                      # warm the forward kernels
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = st.advance(u0.clone(), nsteps)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    ubar = u - target
+    st.adjoint(u0, ubar, 2)                            # warm the adjoint kernels
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, grad = st.adjoint(u0, ubar, nsteps)
+    torch.cuda.synchronize()
+    adj = time.perf_counter() - t0
+    st.close()
+    npts = p.npoints
+    return {"workload": wl.name, "steps": nsteps, "precision": p.precision,
+            "checkpoint_every": math.ceil(math.sqrt(nsteps)),
+            "forward_ms_per_step": 1e3 * fwd / nsteps, "adjoint_ms_per_step": 1e3 * adj / nsteps,
+            "adjoint_over_forward": adj / fwd, "adjoint_updates_per_s": npts * nsteps / adj,
+            "grad_kappa": grad[:p.ncomp], "grad_q": grad[p.ncomp]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -178,6 +215,9 @@ def main():
             out["reduced"][prec] = {"value": npts * args.steps / sec_r, "ms_per_step": 1e3 * sec_r / args.steps,
                                     "speedup_vs_fp64": sec / sec_r, "rel_l2_vs_fp64": float(diff),
                                     "roofline": roof_r}
+
+    if args.adjoint_steps > 0:
+        out["adjoint"] = adjoint_leg(etd, torch, W, args.adjoint_steps)
 
     if not args.no_cpu_baseline:
         import oracle

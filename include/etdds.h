@@ -87,7 +87,8 @@ typedef struct etd_plan etd_plan;
  * closed-form eigenpairs of every A_d and the rational factors of tau*lambda,
  * computed in FP64.  *out receives a new plan (free with etd_plan_destroy).
  * ETD_EINVAL on a malformed problem; ETD_EUNSUPPORTED when a padded grid
- * direction exceeds 256 points or the stage tiles exceed the on-chip limits. */
+ * direction exceeds 1024 points or the stage tiles exceed the on-chip limits
+ * (FP64 tiles of one component hold extents up to 576). */
 etd_status etd_plan_create(const etd_problem* prob, etd_plan** out);
 
 /* Bytes of device workspace the plan needs: eigenvector tables, rational
@@ -149,6 +150,72 @@ etd_status etd_adjoint(const etd_plan* plan, const void* u0_dev, double t0, int 
  * Enabling or disabling also resets them.  Not thread-safe per plan. */
 etd_status etd_timing_enable(etd_plan* plan, int enable);
 etd_status etd_timing_read(etd_plan* plan, double ms[3], long long counts[3]);
+
+/* Tile shapes of the stage kernels (how the mode products of Sec. 3.4 are
+ * blocked on the device; they never change a result, only its speed).  Per
+ * direction d (0 = x, 1 = y, 2 = z), tiles[2d] = 16-row blocks of each product
+ * per wave and tiles[2d+1] = 16-column (outer stages) or 16-line (x stage)
+ * blocks per workgroup; zeros for directions beyond dim.
+ * etd_plan_tiles reports the shapes in use.  etd_plan_set_tiles selects them
+ * ((0, 0) restores the built-in default of a direction); ETD_EUNSUPPORTED if a
+ * shape is not valid there (wave count, LDS, line count), leaving the plan
+ * unchanged.  etd_plan_autotune times every valid shape of every stage on the
+ * uploaded workspace (its stage buffers are scratch) with HIP events on
+ * `stream`, keeps the fastest, and synchronises.  Two-component systems whose
+ * joint tile exceeds the LDS keep their one split shape. */
+etd_status etd_plan_tiles(const etd_plan* plan, int tiles[6]);
+etd_status etd_plan_set_tiles(etd_plan* plan, const int tiles[6]);
+etd_status etd_plan_autotune(etd_plan* plan, void* workspace_dev, void* stream);
+
+/* Batches: `count` (1..4096) independent problems advanced together.  They
+ * must share dim, ncomp and precision; extents, box, coefficients, time step,
+ * reaction and Pade order are per instance.  Instances of one padded shape
+ * form a group whose every stage runs as one persistent launch over all of
+ * its instances' tiles (a descriptor table in the workspace gives each
+ * instance's buffers and tables); groups run on streams of their own,
+ * created by the first upload, forked from and joined back to `stream`.
+ * Instances of equal extent share one eigenvector table.
+ *  - create: ETD_EINVAL as etd_plan_create (message names the instance) or
+ *    when instances differ in dim/ncomp/precision; ETD_EUNSUPPORTED for a
+ *    two-component instance whose joint tile exceeds the LDS.
+ *  - upload: tables and descriptors into one caller-owned workspace of
+ *    etd_batch_workspace_bytes bytes (256-byte aligned); synchronises
+ *    `stream`.  Descriptors hold device addresses, so advance, autotune and
+ *    capture take exactly the uploaded workspace (else ETD_EWORKSPACE).
+ *  - advance: u_dev[i] (a host array of count device pointers) is instance
+ *    i's field, updated in place; each instance's time is t0 + k tau_i.
+ *  - autotune: as etd_plan_autotune, per group (synchronises).
+ *  - tiles: the shapes of instance i's group; groups: number of groups.
+ * Calls on one batch must not overlap. */
+typedef struct etd_batch etd_batch;
+etd_status etd_batch_create(const etd_problem* probs, int count, etd_batch** out);
+etd_status etd_batch_workspace_bytes(const etd_batch* batch, size_t* bytes);
+etd_status etd_batch_upload(etd_batch* batch, void* workspace_dev, size_t bytes, void* stream);
+etd_status etd_batch_advance(etd_batch* batch, void* const* u_dev, double t0, int nsteps, void* workspace_dev,
+                             void* stream);
+etd_status etd_batch_autotune(etd_batch* batch, void* workspace_dev, void* stream);
+etd_status etd_batch_tiles(const etd_batch* batch, int instance, int tiles[6]);
+etd_status etd_batch_groups(const etd_batch* batch, int* groups);
+etd_status etd_batch_destroy(etd_batch* batch);
+
+/* HIP graphs: the device work of one etd_advance (or etd_batch_advance) call
+ * captured from `stream` (which must not be the null stream) into an
+ * executable graph, bound to the given field pointers, workspace, t0 and
+ * nsteps.  Nothing runs during capture.  etd_graph_launch replays that work
+ * on any stream: each replay advances the fields by nsteps steps again, with
+ * the captured times (so time-dependent sources see t0 .. t0 + nsteps tau on
+ * every replay).  The captured work contains kernels only (no memset or copy
+ * nodes).  A plan graph keeps the tile shapes it was captured with.  A batch
+ * graph reads the batch's descriptors at replay, so after etd_batch_autotune,
+ * a new etd_batch_upload or etd_batch_destroy it refuses to launch
+ * (ETD_EINVAL; capture again).  Graphs own host memory only. */
+typedef struct etd_graph etd_graph;
+etd_status etd_graph_capture(const etd_plan* plan, void* u_dev, double t0, int nsteps, void* workspace_dev,
+                             void* stream, etd_graph** out);
+etd_status etd_batch_graph_capture(etd_batch* batch, void* const* u_dev, double t0, int nsteps,
+                                   void* workspace_dev, void* stream, etd_graph** out);
+etd_status etd_graph_launch(etd_graph* graph, void* stream);
+etd_status etd_graph_destroy(etd_graph* graph);
 
 /* Free the plan (host memory and any timing events). */
 etd_status etd_plan_destroy(etd_plan* plan);

@@ -52,6 +52,10 @@ _lib = None
 
 EXPORTS = ("etd_plan_create", "etd_plan_workspace_bytes", "etd_plan_upload", "etd_advance", "etd_compare",
            "etd_plan_table", "etd_timing_enable", "etd_timing_read", "etd_adjoint_workspace_bytes", "etd_adjoint",
+           "etd_plan_tiles", "etd_plan_set_tiles", "etd_plan_autotune",
+           "etd_batch_create", "etd_batch_workspace_bytes", "etd_batch_upload", "etd_batch_advance",
+           "etd_batch_autotune", "etd_batch_tiles", "etd_batch_groups", "etd_batch_destroy",
+           "etd_graph_capture", "etd_batch_graph_capture", "etd_graph_launch", "etd_graph_destroy",
            "etd_plan_destroy", "etd_status_string", "etd_last_error")
 
 
@@ -63,23 +67,44 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2601_06849_amd.build.build()")
         L = ctypes.CDLL(LIB_PATH)
         vp, sz, dp, ip = ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), ctypes.c_int
-        L.etd_plan_create.argtypes = [ctypes.POINTER(etd_problem), ctypes.POINTER(vp)]
-        L.etd_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
-        L.etd_plan_upload.argtypes = [vp, vp, sz, vp]
-        L.etd_advance.argtypes = [vp, vp, ctypes.c_double, ip, vp, vp]
-        L.etd_compare.argtypes = [vp, vp, vp, dp, vp, vp]
-        L.etd_plan_table.argtypes = [vp, ip, ip, ip, dp, sz]
-        L.etd_timing_enable.argtypes = [vp, ip]
-        L.etd_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
-        L.etd_adjoint_workspace_bytes.argtypes = [vp, ip, ctypes.POINTER(sz)]
-        L.etd_adjoint.argtypes = [vp, vp, ctypes.c_double, ip, vp, vp, dp, vp, vp, sz, vp]
-        L.etd_plan_destroy.argtypes = [vp]
+        ipp = ctypes.POINTER(ctypes.c_int)
+        d = ctypes.c_double
+        sig = {
+            "etd_plan_create": [ctypes.POINTER(etd_problem), ctypes.POINTER(vp)],
+            "etd_plan_workspace_bytes": [vp, ctypes.POINTER(sz)],
+            "etd_plan_upload": [vp, vp, sz, vp],
+            "etd_advance": [vp, vp, d, ip, vp, vp],
+            "etd_compare": [vp, vp, vp, dp, vp, vp],
+            "etd_plan_table": [vp, ip, ip, ip, dp, sz],
+            "etd_timing_enable": [vp, ip],
+            "etd_timing_read": [vp, dp, ctypes.POINTER(ctypes.c_longlong)],
+            "etd_adjoint_workspace_bytes": [vp, ip, ctypes.POINTER(sz)],
+            "etd_adjoint": [vp, vp, d, ip, vp, vp, dp, vp, vp, sz, vp],
+            "etd_plan_tiles": [vp, ipp],
+            "etd_plan_set_tiles": [vp, ipp],
+            "etd_plan_autotune": [vp, vp, vp],
+            "etd_batch_create": [ctypes.POINTER(etd_problem), ip, ctypes.POINTER(vp)],
+            "etd_batch_workspace_bytes": [vp, ctypes.POINTER(sz)],
+            "etd_batch_upload": [vp, vp, sz, vp],
+            "etd_batch_advance": [vp, ctypes.POINTER(vp), d, ip, vp, vp],
+            "etd_batch_autotune": [vp, vp, vp],
+            "etd_batch_tiles": [vp, ip, ipp],
+            "etd_batch_groups": [vp, ipp],
+            "etd_batch_destroy": [vp],
+            "etd_graph_capture": [vp, vp, d, ip, vp, vp, ctypes.POINTER(vp)],
+            "etd_batch_graph_capture": [vp, ctypes.POINTER(vp), d, ip, vp, vp, ctypes.POINTER(vp)],
+            "etd_graph_launch": [vp, vp],
+            "etd_graph_destroy": [vp],
+            "etd_plan_destroy": [vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ip
         L.etd_status_string.argtypes = [ip]
         L.etd_status_string.restype = ctypes.c_char_p
         L.etd_last_error.argtypes = []
         L.etd_last_error.restype = ctypes.c_char_p
-        for name in EXPORTS[:11]:
-            getattr(L, name).restype = ip
         _lib = L
     return _lib
 
@@ -194,6 +219,97 @@ def etd_adjoint(plan, u0, t0: float, nsteps: int, ubar_final, ubar0, workspace, 
     return list(grad)
 
 
+def etd_plan_tiles(plan):
+    """[(rows per wave, blocks)] per direction x, y, z ((0, 0) beyond dim)."""
+    t = (ctypes.c_int * 6)()
+    _check(lib().etd_plan_tiles(plan, t))
+    return [(t[0], t[1]), (t[2], t[3]), (t[4], t[5])]
+
+
+def etd_plan_set_tiles(plan, tiles):
+    """tiles: up to three (rows per wave, blocks) pairs for x, y, z; (0, 0) = default."""
+    flat = [0] * 6
+    for d, (rb, cb) in enumerate(tiles):
+        flat[2 * d], flat[2 * d + 1] = int(rb), int(cb)
+    _check(lib().etd_plan_set_tiles(plan, (ctypes.c_int * 6)(*flat)))
+
+
+def etd_plan_autotune(plan, workspace, stream=None):
+    _check(lib().etd_plan_autotune(plan, _ptr(workspace), _stream(stream)))
+
+
+def etd_batch_create(problems) -> ctypes.c_void_p:
+    arr = (etd_problem * len(problems))(*[p if isinstance(p, etd_problem) else problem_struct(p) for p in problems])
+    h = ctypes.c_void_p()
+    _check(lib().etd_batch_create(arr, len(problems), ctypes.byref(h)))
+    return h
+
+
+def etd_batch_workspace_bytes(batch) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().etd_batch_workspace_bytes(batch, ctypes.byref(n)))
+    return int(n.value)
+
+
+def etd_batch_upload(batch, workspace, stream=None):
+    _check(lib().etd_batch_upload(batch, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                  _stream(stream)))
+
+
+def _ptr_array(fields):
+    for f in fields:
+        if not f.is_contiguous():
+            raise ValueError("fields must be contiguous")
+    return (ctypes.c_void_p * len(fields))(*[f.data_ptr() for f in fields])
+
+
+def etd_batch_advance(batch, fields, t0: float, nsteps: int, workspace, stream=None):
+    _check(lib().etd_batch_advance(batch, _ptr_array(fields), float(t0), int(nsteps), _ptr(workspace),
+                                   _stream(stream)))
+
+
+def etd_batch_autotune(batch, workspace, stream=None):
+    _check(lib().etd_batch_autotune(batch, _ptr(workspace), _stream(stream)))
+
+
+def etd_batch_tiles(batch, instance: int):
+    t = (ctypes.c_int * 6)()
+    _check(lib().etd_batch_tiles(batch, int(instance), t))
+    return [(t[0], t[1]), (t[2], t[3]), (t[4], t[5])]
+
+
+def etd_batch_groups(batch) -> int:
+    n = ctypes.c_int()
+    _check(lib().etd_batch_groups(batch, ctypes.byref(n)))
+    return int(n.value)
+
+
+def etd_batch_destroy(batch):
+    _check(lib().etd_batch_destroy(batch))
+
+
+def etd_graph_capture(plan, u, t0: float, nsteps: int, workspace, stream) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().etd_graph_capture(plan, _ptr(u), float(t0), int(nsteps), _ptr(workspace), _stream(stream),
+                                   ctypes.byref(h)))
+    return h
+
+
+def etd_batch_graph_capture(batch, fields, t0: float, nsteps: int, workspace, stream) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().etd_batch_graph_capture(batch, _ptr_array(fields), float(t0), int(nsteps), _ptr(workspace),
+                                         _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def etd_graph_launch(graph, stream=None):
+    _check(lib().etd_graph_launch(graph, _stream(stream)))
+
+
+def etd_graph_destroy(graph):
+    _check(lib().etd_graph_destroy(graph))
+
+
 def etd_plan_destroy(plan):
     _check(lib().etd_plan_destroy(plan))
 
@@ -251,6 +367,20 @@ class Stepper:
                            aws, self.problem.ncomp, self.stream)
         return ubar0, grad
 
+    def autotune(self):
+        etd_plan_autotune(self.plan, self.workspace, self.stream)
+        return self.tiles()
+
+    def tiles(self):
+        return etd_plan_tiles(self.plan)
+
+    def set_tiles(self, tiles):
+        etd_plan_set_tiles(self.plan, tiles)
+
+    def capture(self, u, nsteps: int, stream, t0: float = 0.0):
+        """Graph of advance(u, nsteps, t0) captured from `stream` (not the null stream)."""
+        return Graph(etd_graph_capture(self.plan, u, t0, nsteps, self.workspace, stream), (self, u))
+
     def close(self):
         if self.plan is not None:
             etd_plan_destroy(self.plan)
@@ -262,6 +392,78 @@ class Stepper:
         except Exception:
             pass
 
+
+class Graph:
+    """An executable HIP graph of captured stepper work (see etd_graph_capture)."""
+
+    def __init__(self, handle, keepalive):
+        self.handle = handle
+        self._keep = keepalive   # objects whose memory the graph's kernels use
+
+    def launch(self, stream=None):
+        etd_graph_launch(self.handle, stream)
+
+    def close(self):
+        if self.handle is not None:
+            etd_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent problems (same dim, ncomp, precision) advanced together
+    by grouped persistent launches, with a torch-allocated workspace."""
+
+    def __init__(self, problems, device="cuda:0", stream=None):
+        import torch
+        self.problems = list(problems)
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if self.problems[0].precision == "fp64" else torch.float32
+        self.batch = etd_batch_create(self.problems)
+        nbytes = etd_batch_workspace_bytes(self.batch)
+        self._raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._raw.data_ptr()) % 256
+        self.workspace = self._raw[off:off + nbytes]
+        self.stream = stream
+        etd_batch_upload(self.batch, self.workspace, self.stream)
+
+    def fields(self, u0s):
+        import torch
+        return [torch.as_tensor(np.ascontiguousarray(u), dtype=self.dtype).reshape(p.shape).to(self.device)
+                .contiguous() for p, u in zip(self.problems, u0s)]
+
+    def advance(self, fields, nsteps: int, t0: float = 0.0):
+        etd_batch_advance(self.batch, fields, t0, nsteps, self.workspace, self.stream)
+        return fields
+
+    def autotune(self):
+        etd_batch_autotune(self.batch, self.workspace, self.stream)
+
+    def tiles(self, instance: int):
+        return etd_batch_tiles(self.batch, instance)
+
+    def groups(self) -> int:
+        return etd_batch_groups(self.batch)
+
+    def capture(self, fields, nsteps: int, stream, t0: float = 0.0) -> Graph:
+        h = etd_batch_graph_capture(self.batch, fields, t0, nsteps, self.workspace, stream)
+        return Graph(h, (self, list(fields)))
+
+    def close(self):
+        if self.batch is not None:
+            etd_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 # --------------------------------------------------------------------------
 # autograd: U_N = advance(u0; kappa, q) with the hand-written adjoint

@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -202,6 +203,7 @@ struct RxnArgs {
     double ac_mu;          // sum_d mu_d, d psi / d kappa per unit ue (AC_MMS)
     double exp_lt;         // e^{-lam t} at the stage's time (AC_MMS)
     const double* sines;   // [3][kMaxPadded] sin(pi (x_i - lo)/L), 0 on the padding
+    double tau;            // the instance's time step (grouped launches form t from it)
 };
 
 // Exact solution and psi of the manufactured Allen-Cahn problem at node
@@ -402,8 +404,8 @@ __device__ __forceinline__ T react_coupled(const RxnArgs& r, int comp, T mine, T
 // of T (the contracted index contiguous, so a lane's B fragment is one
 // vector read), first the inputs (and f of them), then the scaled spectral
 // coefficients.
-template <typename M, int NC, bool FIRST, int RB, int CB, int MAXT>
-__global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
+template <typename M, int NC, bool FIRST, int RB, int CB>
+__device__ __forceinline__ void outer_tile(const OuterArgs& a, long tile) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
     typedef typename Vec16<T>::type TV;
@@ -422,8 +424,8 @@ __global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
-    const int cb = blockIdx.x % a.ncb;
-    const long bt = blockIdx.x / a.ncb;
+    const int cb = int(tile % a.ncb);
+    const long bt = tile / a.ncb;
     const long gbase = bt * a.sb + long(cb) * NCOL;
     const T* __restrict__ in0 = static_cast<const T*>(a.in0);
     const T* __restrict__ in1 = static_cast<const T*>(a.in1);
@@ -538,6 +540,11 @@ __global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
         }
 }
 
+template <typename M, int NC, bool FIRST, int RB, int CB, int MAXT>
+__global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
+    outer_tile<M, NC, FIRST, RB, CB>(a, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // x stage: contraction along the contiguous direction, both RK stages fused
 // ---------------------------------------------------------------------------
@@ -562,8 +569,8 @@ struct XArgs {
 // the spectral/physical x rows of blocks RB*w .. RB*w+RB-1 of every product,
 // for all CB line blocks.  LDS: [2*NC][16*CB lines][NP + pad]; arrays 0..NC-1
 // hold w3, then c, then e; arrays NC..2NC-1 hold w4, then d.
-template <typename M, int NC, int RB, int CB, int MAXT>
-__global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
+template <typename M, int NC, int RB, int CB>
+__device__ __forceinline__ void x_tile(const XArgs& a, long tile) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
     typedef typename Vec16<T>::type TV;
@@ -580,7 +587,7 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
-    const long line0 = long(blockIdx.x) * NL;
+    const long line0 = tile * NL;
     const T* __restrict__ w3 = static_cast<const T*>(a.w3);
     const T* __restrict__ w4 = static_cast<const T*>(a.w4);
     const void* __restrict__ P = a.P;
@@ -711,6 +718,65 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
                 for (int e = 0; e < 4; ++e)
                     o[M::row(lg, e)] = V[r][c * CB + cb][e] + tau * acc[r][c * CB + cb][e];
             }
+    }
+}
+
+template <typename M, int NC, int RB, int CB, int MAXT>
+__global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
+    x_tile<M, NC, RB, CB>(a, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped (batched) launches: one persistent launch runs a stage for every
+// instance of a shape class.  Instance i owns tiles start[i] .. start[i+1]-1
+// of the launch; workgroups stride over the tiles, find their instance by
+// binary search and run the same tile body with that instance's arguments.
+// ---------------------------------------------------------------------------
+
+template <typename A>
+struct Group {
+    const A* args;       // per-instance stage arguments (device memory)
+    const long* start;   // [n + 1] first tile of each instance
+    int n;
+    long ntiles;
+    double t0;           // time of the call's first step
+    int k;               // the stage's time is t0 + k tau_i
+};
+
+template <typename A>
+__device__ __forceinline__ int group_instance(const Group<A>& g, long tile) {
+    int lo = 0, hi = g.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.start[mid] <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void group_time(RxnArgs& r, double t0, int k) {
+    if (r.kind == ETD_RXN_AC_MMS) r.exp_lt = exp(-r.p[0] * (t0 + k * r.tau));
+}
+
+template <typename M, int NC, bool FIRST, int RB, int CB, int MAXT>
+__global__ __launch_bounds__(MAXT) void outer_group(Group<OuterArgs> g) {
+    for (long t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
+        const int i = group_instance(g, t);
+        OuterArgs a = g.args[i];
+        group_time(a.rxn, g.t0, g.k);
+        outer_tile<M, NC, FIRST, RB, CB>(a, t - g.start[i]);
+        __syncthreads();   // the next tile restages the LDS
+    }
+}
+
+template <typename M, int NC, int RB, int CB, int MAXT>
+__global__ __launch_bounds__(MAXT) void x_group(Group<XArgs> g) {
+    for (long t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
+        const int i = group_instance(g, t);
+        XArgs a = g.args[i];
+        group_time(a.rxn, g.t0, g.k);
+        x_tile<M, NC, RB, CB>(a, t - g.start[i]);
+        __syncthreads();
     }
 }
 
@@ -1439,6 +1505,7 @@ RxnArgs rxn_args(const Plan& pl, const char* ws, double t) {
     r.ac_rate = 0.0;
     r.ac_mu = 0.0;
     r.exp_lt = 0.0;
+    r.tau = p.tau;
     if (p.rxn == ETD_RXN_AC_MMS) {
         const double lam = p.rxn_param[0];
         double mu = 0.0;
@@ -1470,46 +1537,144 @@ hipError_t set_lds(K kernel, size_t bytes, size_t& done) {
     return e;
 }
 
-// Tile shape.  Every wave owns RB = rows_per_wave(NP) 16-row blocks of each
-// product, so a tile needs NP/(16 RB) waves (at most 8 up to NP = 256, 16
-// beyond, with the matching launch bound).  The x stage spans two 16-line
-// blocks when its LDS footprint fits at NP <= 256 (each P fragment then
-// feeds twice the MFMAs; FP64 systems would spill registers and stay at one
-// block).  The outer stages keep one 16-column block in FP64, where two
-// workgroups per CU (64 KB LDS each at NP = 256) beat the wider tile, and
-// take two blocks in FP32.  Measured on the 255^3 workload.
-template <typename T, int NC>
-constexpr bool wide_tiles() { return sizeof(T) == 4 || NC == 1; }
-template <typename T, int NC>
-constexpr bool wide_outer_tiles() { return sizeof(T) == 4; }
+// Tile shape of a stage launch.  Every wave owns `rb` 16-row blocks of each
+// product (a tile has NP/(16 rb) waves) and a tile spans `cb` 16-column
+// (outer stages) or 16-line (x stage) blocks, so that each P fragment read
+// from L2 feeds 2*NC*cb MFMAs.  Instantiated (rb, cb, launch bound):
+// (2,1,512), (2,1,1024), (4,1,1024), (2,2,512); with an FP32 state also
+// (4,1,512), and for single-component x stages (2,4,512).
+//
+// The default shape, measured on the 255^3 workload: rb = 2 up to NP = 512
+// and 4 beyond; two column blocks in the outer stages only with an FP32 state
+// (in FP64 two workgroups per CU at one block beat the wider tile); x tiles
+// of four line blocks for single-component FP32-state systems, two for any
+// other FP32 state or single-component FP64 system (a two-component FP64
+// tile would spill).  An autotuned plan times every valid shape instead.
+struct TileShape {
+    int rb = 0, cb = 0;   // rb == 0: use the default
+};
 
-int tile_threads(int NP) { return 64 * (NP / (16 * rows_per_wave(NP))); }
+int shape_threads(int NP, int rb) { return 64 * (NP / (16 * rb)); }
 
-// Launch kern<RB, MAXT> for the padded length NP: (2, 512) up to 256,
-// (2, 1024) up to 512, (4, 1024) up to 1024.
+template <typename T>
+bool shape_rows_ok(int NP, int rb) {
+    if (rb != 2 && rb != 4) return false;
+    if (NP % (16 * rb) != 0 || NP / (16 * rb) > kMaxWaves) return false;
+    return !(rb == 4 && shape_threads(NP, rb) <= 512 && sizeof(T) != 4);
+}
+
+template <typename T, int NC>
+bool outer_shape_ok(int NP, TileShape t) {
+    if (!shape_rows_ok<T>(NP, t.rb)) return false;
+    if (t.cb == 2) {
+        if (t.rb != 2 || shape_threads(NP, t.rb) > 512) return false;
+    } else if (t.cb != 1) {
+        return false;
+    }
+    return outer_lds_bytes(NP, 2 * NC, t.cb, sizeof(T)) <= kMaxLds;
+}
+
+template <typename T, int NC>
+bool x_shape_ok(int NP, long nlines, TileShape t) {
+    if (!shape_rows_ok<T>(NP, t.rb)) return false;
+    if (t.cb == 2 || t.cb == 4) {
+        if (t.rb != 2 || shape_threads(NP, t.rb) > 512) return false;
+        if (t.cb == 4 && !(sizeof(T) == 4 && NC == 1)) return false;
+    } else if (t.cb != 1) {
+        return false;
+    }
+    if (nlines % (16 * t.cb) != 0) return false;
+    return x_lds_bytes(NP, 2 * NC, t.cb, sizeof(T)) <= kMaxLds;
+}
+
+template <typename T, int NC>
+TileShape default_outer_shape(int NP) {
+    if (sizeof(T) == 4 && outer_shape_ok<T, NC>(NP, TileShape{2, 2})) return TileShape{2, 2};
+    return TileShape{rows_per_wave(NP), 1};
+}
+
+template <typename T, int NC>
+TileShape default_x_shape(int NP, long nlines) {
+    if (sizeof(T) == 4 && NC == 1 && x_shape_ok<T, NC>(NP, nlines, TileShape{2, 4})) return TileShape{2, 4};
+    if ((sizeof(T) == 4 || NC == 1) && x_shape_ok<T, NC>(NP, nlines, TileShape{2, 2})) return TileShape{2, 2};
+    return TileShape{rows_per_wave(NP), 1};
+}
+
+int tile_threads(int NP) { return shape_threads(NP, rows_per_wave(NP)); }
+
+// Launch kern<RB, MAXT> for the padded length NP with the default rows per
+// wave: (2, 512) up to 256, (2, 1024) up to 512, (4, 1024) up to 1024.
 #define DISPATCH_SHAPE(NP, KERNEL, ...)                                   \
     ((NP) <= 256 ? KERNEL(2, 512, __VA_ARGS__)                            \
                  : ((NP) <= 512 ? KERNEL(2, 1024, __VA_ARGS__) : KERNEL(4, 1024, __VA_ARGS__)))
 
+// Resident workgroups of a grouped kernel on the whole device (persistent
+// grid size), at most `ntiles`.
+template <typename K>
+long persistent_grid(K kernel, int threads, size_t lds, long ntiles) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), threads, lds) !=
+            hipSuccess ||
+        per_cu < 1 || cus < 1)
+        return ntiles;
+    return std::max(1L, std::min(ntiles, long(per_cu) * cus));
+}
+
 template <typename M, int NC, bool FIRST, int RB, int CB, int MAXT>
-etd_status launch_outer_k(const OuterArgs& a, long nblocks, hipStream_t s) {
+etd_status launch_outer_k(const OuterArgs& a, long ntiles, hipStream_t s) {
     typedef typename M::elem T;
     const size_t lds = outer_lds_bytes(a.NP, 2 * NC, CB, sizeof(T));
     auto k = outer_stage<M, NC, FIRST, RB, CB, MAXT>;
     static size_t done = 0;
     HIP_TRY(set_lds(k, lds, done), "outer stage LDS attribute");
-    hipLaunchKernelGGL(k, dim3(unsigned(nblocks)), dim3(tile_threads(a.NP)), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(unsigned(ntiles)), dim3(shape_threads(a.NP, RB)), lds, s, a);
     HIP_TRY(hipGetLastError(), "outer stage launch");
     return ETD_OK;
 }
 
 #define OUTER_K(RB, MAXT, M, NC, FIRST, CB, a, nb, s) launch_outer_k<M, NC, FIRST, RB, CB, MAXT>(a, nb, s)
 
-// One outer stage over all components.  a.ncb and nblocks count 16-column
-// blocks (halved for 32-wide tiles).  Systems whose joint tile exceeds the
-// LDS run one component per launch.
+template <typename M, int NC, bool FIRST, int RB, int CB, int MAXT>
+etd_status launch_outer_group_k(const Group<OuterArgs>& g, int NP, hipStream_t s) {
+    typedef typename M::elem T;
+    const size_t lds = outer_lds_bytes(NP, 2 * NC, CB, sizeof(T));
+    auto k = outer_group<M, NC, FIRST, RB, CB, MAXT>;
+    static size_t done = 0;
+    HIP_TRY(set_lds(k, lds, done), "grouped outer stage LDS attribute");
+    const int thr = shape_threads(NP, RB);
+    hipLaunchKernelGGL(k, dim3(unsigned(persistent_grid(k, thr, lds, g.ntiles))), dim3(thr), lds, s, g);
+    HIP_TRY(hipGetLastError(), "grouped outer stage launch");
+    return ETD_OK;
+}
+
+// Pick the instantiation of a valid shape: L is launch_outer_k or
+// launch_outer_group_k applied through a generic lambda.
+template <typename T, int NC, typename L>
+etd_status outer_by_shape(int NP, TileShape t, L&& launch) {
+    const bool small = shape_threads(NP, t.rb) <= 512;
+    if (t.cb == 2) return launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{},
+                                 std::integral_constant<int, 512>{});
+    if (t.rb == 2)
+        return small ? launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{},
+                              std::integral_constant<int, 512>{})
+                     : launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{},
+                              std::integral_constant<int, 1024>{});
+    if (!small)
+        return launch(std::integral_constant<int, 4>{}, std::integral_constant<int, 1>{},
+                      std::integral_constant<int, 1024>{});
+    if constexpr (sizeof(T) == 4)
+        return launch(std::integral_constant<int, 4>{}, std::integral_constant<int, 1>{},
+                      std::integral_constant<int, 512>{});
+    return fail(ETD_EUNSUPPORTED, "tile shape not available at this precision");
+}
+
+// One outer stage over all components of one instance.  a.ncb and ncols16
+// count 16-column blocks.  Systems whose joint tile exceeds the LDS run one
+// component per launch with the default rows per wave.
 template <typename M, int NC, bool FIRST>
-etd_status launch_outer(OuterArgs a, long nblocks, hipStream_t s) {
+etd_status launch_outer(OuterArgs a, long ncols16, TileShape t, hipStream_t s) {
     typedef typename M::elem T;
     if (NC == 2 && !outer_fused(a.NP, NC, sizeof(T))) {
         for (int c = 0; c < NC; ++c) {
@@ -1522,16 +1687,17 @@ etd_status launch_outer(OuterArgs a, long nblocks, hipStream_t s) {
             b.diag = static_cast<const T*>(a.diag) + c * a.diag_cstride;
             b.other = FIRST ? static_cast<const T*>(a.in0) + (1 - c) * a.sc : nullptr;
             b.comp = c;
-            const etd_status st = DISPATCH_SHAPE(a.NP, OUTER_K, M, 1, FIRST, 1, b, nblocks, s);
+            const etd_status st = DISPATCH_SHAPE(a.NP, OUTER_K, M, 1, FIRST, 1, b, ncols16, s);
             if (st != ETD_OK) return st;
         }
         return ETD_OK;
     }
-    if (wide_outer_tiles<T, NC>() && a.NP <= 256 && outer_lds_bytes(a.NP, 2 * NC, 2, sizeof(T)) <= kMaxLds) {
-        a.ncb /= 2;
-        return launch_outer_k<M, NC, FIRST, 2, 2, 512>(a, nblocks / 2, s);
-    }
-    return DISPATCH_SHAPE(a.NP, OUTER_K, M, NC, FIRST, 1, a, nblocks, s);
+    if (t.rb == 0) t = default_outer_shape<T, NC>(a.NP);
+    a.ncb /= t.cb;
+    return outer_by_shape<T, NC>(a.NP, t, [&](auto rb, auto cb, auto mt) {
+        return launch_outer_k<M, NC, FIRST, decltype(rb)::value, decltype(cb)::value, decltype(mt)::value>(
+            a, ncols16 / decltype(cb)::value, s);
+    });
 }
 
 template <typename M, int NC, int RB, int CB, int MAXT>
@@ -1541,12 +1707,48 @@ etd_status launch_x_k(const XArgs& a, long nlines, hipStream_t s) {
     auto k = x_stage<M, NC, RB, CB, MAXT>;
     static size_t done = 0;
     HIP_TRY(set_lds(k, lds, done), "x stage LDS attribute");
-    hipLaunchKernelGGL(k, dim3(unsigned(nlines / (16 * CB))), dim3(tile_threads(a.NP)), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(unsigned(nlines / (16 * CB))), dim3(shape_threads(a.NP, RB)), lds, s, a);
     HIP_TRY(hipGetLastError(), "x stage launch");
     return ETD_OK;
 }
 
-#define X_K(RB, MAXT, M, NC, CB, a, nl, s) launch_x_k<M, NC, RB, CB, MAXT>(a, nl, s)
+template <typename M, int NC, int RB, int CB, int MAXT>
+etd_status launch_x_group_k(const Group<XArgs>& g, int NP, hipStream_t s) {
+    typedef typename M::elem T;
+    const size_t lds = x_lds_bytes(NP, 2 * NC, CB, sizeof(T));
+    auto k = x_group<M, NC, RB, CB, MAXT>;
+    static size_t done = 0;
+    HIP_TRY(set_lds(k, lds, done), "grouped x stage LDS attribute");
+    const int thr = shape_threads(NP, RB);
+    hipLaunchKernelGGL(k, dim3(unsigned(persistent_grid(k, thr, lds, g.ntiles))), dim3(thr), lds, s, g);
+    HIP_TRY(hipGetLastError(), "grouped x stage launch");
+    return ETD_OK;
+}
+
+template <typename T, int NC, typename L>
+etd_status x_by_shape(int NP, TileShape t, L&& launch) {
+    const bool small = shape_threads(NP, t.rb) <= 512;
+    if (t.cb == 4) {
+        if constexpr (sizeof(T) == 4 && NC == 1)
+            return launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{},
+                          std::integral_constant<int, 512>{});
+        return fail(ETD_EUNSUPPORTED, "tile shape not available for this system");
+    }
+    if (t.cb == 2) return launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{},
+                                 std::integral_constant<int, 512>{});
+    if (t.rb == 2)
+        return small ? launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{},
+                              std::integral_constant<int, 512>{})
+                     : launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{},
+                              std::integral_constant<int, 1024>{});
+    if (!small)
+        return launch(std::integral_constant<int, 4>{}, std::integral_constant<int, 1>{},
+                      std::integral_constant<int, 1024>{});
+    if constexpr (sizeof(T) == 4)
+        return launch(std::integral_constant<int, 4>{}, std::integral_constant<int, 1>{},
+                      std::integral_constant<int, 512>{});
+    return fail(ETD_EUNSUPPORTED, "tile shape not available at this precision");
+}
 
 template <typename M, int RB, int MAXT, bool SECOND>
 etd_status launch_xsplit_k(const XSplitArgs& a, long nlines, hipStream_t s) {
@@ -1562,10 +1764,10 @@ etd_status launch_xsplit_k(const XSplitArgs& a, long nlines, hipStream_t s) {
 
 #define XS_K(RB, MAXT, M, SECOND, a, nl, s) launch_xsplit_k<M, RB, MAXT, SECOND>(a, nl, s)
 
-// The x stage over all components.  `scratch` receives W when a system is
-// split (its joint tile exceeds the LDS).
+// The x stage over all components of one instance.  `scratch` receives W
+// when a system is split (its joint tile exceeds the LDS).
 template <typename M, int NC>
-etd_status launch_x(const XArgs& a, long nlines, typename M::elem* scratch, hipStream_t s) {
+etd_status launch_x(const XArgs& a, long nlines, TileShape t, typename M::elem* scratch, hipStream_t s) {
     typedef typename M::elem T;
     if (NC == 2 && !x_fused(a.NP, NC, sizeof(T))) {
         XSplitArgs b{};
@@ -1596,15 +1798,13 @@ etd_status launch_x(const XArgs& a, long nlines, typename M::elem* scratch, hipS
         }
         return ETD_OK;
     }
-    // FP32 state: 64-line tiles when the LDS and the line count allow (four
-    // blocks per P fragment; the 16-cycle BF16 steps need it most)
-    if constexpr (sizeof(T) == 4 && NC == 1)
-        if (a.NP <= 256 && nlines % 64 == 0 && x_lds_bytes(a.NP, 2 * NC, 4, sizeof(T)) <= kMaxLds)
-            return launch_x_k<M, NC, 2, 4, 512>(a, nlines, s);
-    if (wide_tiles<T, NC>() && a.NP <= 256 && x_lds_bytes(a.NP, 2 * NC, 2, sizeof(T)) <= kMaxLds)
-        return launch_x_k<M, NC, 2, 2, 512>(a, nlines, s);
-    return DISPATCH_SHAPE(a.NP, X_K, M, NC, 1, a, nlines, s);
+    if (t.rb == 0) t = default_x_shape<T, NC>(a.NP, nlines);
+    return x_by_shape<T, NC>(a.NP, t, [&](auto rb, auto cb, auto mt) {
+        return launch_x_k<M, NC, decltype(rb)::value, decltype(cb)::value, decltype(mt)::value>(a, nlines, s);
+    });
 }
+
+TileShape plan_tile(const Plan& pl, int d) { return TileShape{pl.tile_rb[d], pl.tile_cb[d]}; }
 
 etd_status timer_mark(StageTimer& t, int kind, bool begin, hipStream_t s);
 
@@ -1618,91 +1818,130 @@ etd_status timer_mark(StageTimer& t, int kind, bool begin, hipStream_t s);
         if (st_ != ETD_OK) return st_;                              \
     } while (0)
 
+// Arguments of one step's stage launches for one instance whose workspace
+// region starts at ws (times are filled in per step).  Pdir[d] is the P table
+// the instance uses for direction d (a batch shares one per extent).
+// outer[k] / ocols[k]: the k-th outer stage and its 16-column blocks;
+// nlines: x lines.  Default tile shapes are applied by the launchers.
+struct StepArgs {
+    int nouter = 0;
+    OuterArgs outer[2];
+    long ocols[2] = {0, 0};
+    int odir[2] = {0, 0};   // contracted direction of each outer stage
+    XArgs x;
+    long nlines = 0;
+    void* split_scratch = nullptr;   // W of a split x stage
+};
+
+StepArgs step_args(const Plan& pl, char* ws, const void* const Pdir[3]) {
+    const int px = pl.np[0], py = pl.np[1], pz = pl.np[2];
+    const long sc = long(px) * py * pz;
+    const size_t e = pl.elem;
+    char* U = ws + pl.lay.field[0];
+    char* WA = ws + pl.lay.field[1];
+    char* WB = ws + pl.lay.field[2];
+    char* WC = ws + pl.lay.field[3];
+    char* WD = ws + pl.lay.field[4];
+    const char* diag = ws + pl.lay.diag;
+    const long dstride = long(pl.diag_stride);
+    const long dcs = long(kDiagSlots) * dstride;
+    StepArgs a;
+    OuterArgs o{};
+    o.diag_cstride = dcs;
+    o.sc = sc;
+    o.npx = px;
+    o.npy = py;
+    o.dim = pl.dim;
+    const char* w3;
+    const char* w4;
+    if (pl.dim == 3) {
+        // z stage: contracted index z (stride px*py), columns (y, x)
+        o.in0 = U;
+        o.in1 = nullptr;
+        o.out0 = WA;
+        o.out1 = WB;
+        o.P = Pdir[2];
+        o.diag = diag + long(kDiagZ) * dstride * e;
+        o.NP = pz;
+        o.ncb = px * py / 16;
+        o.sk = long(px) * py;
+        o.sb = 0;
+        a.outer[0] = o;
+        a.ocols[0] = o.ncb;
+        a.odir[0] = 2;
+        // y stage: contracted index y (stride px), columns x, batches z
+        o.in0 = WA;
+        o.in1 = WB;
+        o.out0 = WC;
+        o.out1 = WD;
+        o.P = Pdir[1];
+        o.diag = diag + long(kDiagY) * dstride * e;
+        o.NP = py;
+        o.ncb = px / 16;
+        o.sk = px;
+        o.sb = long(px) * py;
+        a.outer[1] = o;
+        a.ocols[1] = long(o.ncb) * pz;
+        a.odir[1] = 1;
+        a.nouter = 2;
+        w3 = WC;
+        w4 = WD;
+        a.split_scratch = WA;
+    } else {
+        o.in0 = U;
+        o.in1 = nullptr;
+        o.out0 = WA;
+        o.out1 = WB;
+        o.P = Pdir[1];
+        o.diag = diag + long(kDiagY) * dstride * e;
+        o.NP = py;
+        o.ncb = px / 16;
+        o.sk = px;
+        o.sb = 0;
+        a.outer[0] = o;
+        a.ocols[0] = o.ncb;
+        a.odir[0] = 1;
+        a.nouter = 1;
+        w3 = WA;
+        w4 = WB;
+        a.split_scratch = WC;
+    }
+    XArgs& x = a.x;
+    x = XArgs{};
+    x.w3 = w3;
+    x.w4 = w4;
+    x.out = U;
+    x.P = Pdir[0];
+    x.diag = diag + long(kDiagX1) * dstride * e;
+    x.diag_sstride = dstride;
+    x.diag_cstride = dcs;
+    x.NP = px;
+    x.sc = sc;
+    x.npy = py;
+    x.tau = pl.prob.tau;
+    x.Wout = nullptr;
+    a.nlines = long(py) * pz;
+    return a;
+}
+
 template <typename M, int NC>
 etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int nsteps, hipStream_t s,
                      typename M::elem* w_out = nullptr) {
     typedef typename M::elem T;
-    const int px = pl.np[0], py = pl.np[1], pz = pl.np[2];
-    const long sc = long(px) * py * pz;
-    T* U = reinterpret_cast<T*>(ws + pl.lay.field[0]);
-    T* WA = reinterpret_cast<T*>(ws + pl.lay.field[1]);
-    T* WB = reinterpret_cast<T*>(ws + pl.lay.field[2]);
-    T* WC = reinterpret_cast<T*>(ws + pl.lay.field[3]);
-    T* WD = reinterpret_cast<T*>(ws + pl.lay.field[4]);
-    const T* diag = reinterpret_cast<const T*>(ws + pl.lay.diag);
-    const long dstride = long(pl.diag_stride);
-    const long dcs = long(kDiagSlots) * dstride;
+    const void* Pdir[3] = {ws + pl.lay.P[0], ws + pl.lay.P[1], ws + pl.lay.P[2]};
+    StepArgs a = step_args(pl, ws, Pdir);
+    a.x.Wout = w_out;
     const double tau = pl.prob.tau;
-
     for (int step = 0; step < nsteps; ++step) {
         const double tn = t0 + step * tau;
         const double tn1 = t0 + (step + 1) * tau;
-        OuterArgs o{};
-        o.diag_cstride = dcs;
-        o.sc = sc;
-        o.npx = px;
-        o.npy = py;
-        o.dim = pl.dim;
-        o.rxn = rxn_args(pl, ws, tn);
-        const T* w3;
-        const T* w4;
-        if (pl.dim == 3) {
-            // z stage: contracted index z (stride px*py), columns (y, x)
-            o.in0 = U;
-            o.in1 = nullptr;
-            o.out0 = WA;
-            o.out1 = WB;
-            o.P = ws + pl.lay.P[2];
-            o.diag = diag + long(kDiagZ) * dstride;
-            o.NP = pz;
-            o.ncb = px * py / 16;
-            o.sk = long(px) * py;
-            o.sb = 0;
-            TIMED(0, (launch_outer<M, NC, true>(o, o.ncb, s)));
-            // y stage: contracted index y (stride px), columns x, batches z
-            o.in0 = WA;
-            o.in1 = WB;
-            o.out0 = WC;
-            o.out1 = WD;
-            o.P = ws + pl.lay.P[1];
-            o.diag = diag + long(kDiagY) * dstride;
-            o.NP = py;
-            o.ncb = px / 16;
-            o.sk = px;
-            o.sb = long(px) * py;
-            TIMED(1, (launch_outer<M, NC, false>(o, long(o.ncb) * pz, s)));
-            w3 = WC;
-            w4 = WD;
-        } else {
-            o.in0 = U;
-            o.in1 = nullptr;
-            o.out0 = WA;
-            o.out1 = WB;
-            o.P = ws + pl.lay.P[1];
-            o.diag = diag + long(kDiagY) * dstride;
-            o.NP = py;
-            o.ncb = px / 16;
-            o.sk = px;
-            o.sb = 0;
-            TIMED(0, (launch_outer<M, NC, true>(o, o.ncb, s)));
-            w3 = WA;
-            w4 = WB;
+        for (int k = 0; k < a.nouter; ++k) {
+            a.outer[k].rxn = rxn_args(pl, ws, tn);
+            if (k == 0) TIMED(0, (launch_outer<M, NC, true>(a.outer[0], a.ocols[0], plan_tile(pl, a.odir[0]), s)));
+            else TIMED(1, (launch_outer<M, NC, false>(a.outer[1], a.ocols[1], plan_tile(pl, a.odir[1]), s)));
         }
-        XArgs x{};
-        x.w3 = w3;
-        x.w4 = w4;
-        x.out = U;
-        x.P = ws + pl.lay.P[0];
-        x.diag = diag + long(kDiagX1) * dstride;
-        x.diag_sstride = dstride;
-        x.diag_cstride = dcs;
-        x.NP = px;
-        x.sc = sc;
-        x.npy = py;
-        x.tau = tau;
-        x.rxn = rxn_args(pl, ws, tn1);
-        x.Wout = w_out;
-        TIMED(2, (launch_x<M, NC>(x, long(py) * pz, pl.dim == 3 ? WA : WC, s)));
+        a.x.rxn = rxn_args(pl, ws, tn1);
+        TIMED(2, (launch_x<M, NC>(a.x, a.nlines, plan_tile(pl, 0), static_cast<T*>(a.split_scratch), s)));
     }
     return ETD_OK;
 }
@@ -1985,6 +2224,405 @@ etd_status timer_mark(StageTimer& t, int kind, bool begin, hipStream_t s) {
     return ETD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuning: time every valid tile shape of a stage and keep the fastest.
+// All shapes compute every output with the same operations in the same
+// order, so the choice changes the speed, never the result.
+// ---------------------------------------------------------------------------
+
+template <typename T, int NC>
+std::vector<TileShape> outer_candidates(int NP) {
+    std::vector<TileShape> v;
+    for (int rb : {2, 4})
+        for (int cb : {1, 2})
+            if (outer_shape_ok<T, NC>(NP, TileShape{rb, cb})) v.push_back(TileShape{rb, cb});
+    return v;
+}
+
+template <typename T, int NC>
+std::vector<TileShape> x_candidates(int NP, long nlines) {
+    std::vector<TileShape> v;
+    for (int rb : {2, 4})
+        for (int cb : {1, 2, 4})
+            if (x_shape_ok<T, NC>(NP, nlines, TileShape{rb, cb})) v.push_back(TileShape{rb, cb});
+    return v;
+}
+
+// Mean milliseconds of `launch` over `reps` launches after one warm-up.
+template <typename L>
+etd_status time_launches(L&& launch, int reps, hipStream_t s, float& ms) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "autotune event");
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he, "autotune event");
+    }
+    etd_status st = launch();
+    if (st == ETD_OK) {
+        he = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st == ETD_OK; ++r) st = launch();
+        if (he == hipSuccess) he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (st == ETD_OK && he != hipSuccess) st = hip_fail(he, "autotune timing");
+        ms /= float(reps);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+constexpr int kTuneReps = 5;
+constexpr int kMaxBatch = 4096;   // instances per batch
+
+template <typename M, int NC>
+etd_status autotune_plan_t(Plan& pl, char* ws, hipStream_t s) {
+    typedef typename M::elem T;
+    if (NC == 2 && (!x_fused(pl.np[0], NC, sizeof(T)) ||
+                    !outer_fused(pl.np[1], NC, sizeof(T)) || (pl.dim == 3 && !outer_fused(pl.np[2], NC, sizeof(T)))))
+        return ETD_OK;   // split systems run one fixed shape
+    const void* Pdir[3] = {ws + pl.lay.P[0], ws + pl.lay.P[1], ws + pl.lay.P[2]};
+    StepArgs a = step_args(pl, ws, Pdir);
+    for (int k = 0; k < a.nouter; ++k) a.outer[k].rxn = rxn_args(pl, ws, 0.0);
+    a.x.rxn = rxn_args(pl, ws, pl.prob.tau);
+    for (int k = 0; k < a.nouter; ++k) {
+        const int d = a.odir[k];
+        TileShape best{};
+        float best_ms = 0.f;
+        for (TileShape t : outer_candidates<T, NC>(pl.np[d])) {
+            float ms = 0.f;
+            const etd_status st = time_launches([&]() {
+                return k == 0 ? launch_outer<M, NC, true>(a.outer[0], a.ocols[0], t, s)
+                              : launch_outer<M, NC, false>(a.outer[1], a.ocols[1], t, s);
+            }, kTuneReps, s, ms);
+            if (st != ETD_OK) return st;
+            if (best.rb == 0 || ms < best_ms) {
+                best = t;
+                best_ms = ms;
+            }
+        }
+        pl.tile_rb[d] = best.rb;
+        pl.tile_cb[d] = best.cb;
+    }
+    TileShape best{};
+    float best_ms = 0.f;
+    for (TileShape t : x_candidates<T, NC>(pl.np[0], a.nlines)) {
+        float ms = 0.f;
+        const etd_status st = time_launches(
+            [&]() { return launch_x<M, NC>(a.x, a.nlines, t, static_cast<T*>(a.split_scratch), s); }, kTuneReps, s,
+            ms);
+        if (st != ETD_OK) return st;
+        if (best.rb == 0 || ms < best_ms) {
+            best = t;
+            best_ms = ms;
+        }
+    }
+    pl.tile_rb[0] = best.rb;
+    pl.tile_cb[0] = best.cb;
+    return ETD_OK;
+}
+
+// Validate and resolve a tile request for one direction of a plan: (0, 0)
+// selects the default shape.
+template <typename T, int NC>
+etd_status resolve_tile(const Plan& pl, int d, TileShape t, TileShape& out) {
+    const int NP = pl.np[d];
+    const long nlines = long(pl.np[1]) * pl.np[2];
+    if (t.rb == 0 && t.cb == 0) {
+        out = d == 0 ? default_x_shape<T, NC>(NP, nlines) : default_outer_shape<T, NC>(NP);
+        return ETD_OK;
+    }
+    const bool ok = d == 0 ? x_shape_ok<T, NC>(NP, nlines, t) : outer_shape_ok<T, NC>(NP, t);
+    if (!ok) return fail(ETD_EUNSUPPORTED, "tile shape not valid for this direction");
+    out = t;
+    return ETD_OK;
+}
+
+etd_status resolve_tile_any(const Plan& pl, int d, TileShape t, TileShape& out) {
+    if (pl.elem == 8) return pl.nc == 1 ? resolve_tile<double, 1>(pl, d, t, out) : resolve_tile<double, 2>(pl, d, t, out);
+    return pl.nc == 1 ? resolve_tile<float, 1>(pl, d, t, out) : resolve_tile<float, 2>(pl, d, t, out);
+}
+
+// ---------------------------------------------------------------------------
+// Batches: many independent instances (same dimension, component count and
+// precision; any extents, coefficients, step, reaction and Pade order)
+// advanced together.  Instances of one padded shape form a group; each group
+// runs every stage of every step as ONE persistent grouped launch over all of
+// its instances' tiles, on a stream of its own, so groups of different shapes
+// overlap on the device.  Instances of equal extent share one P table.
+// ---------------------------------------------------------------------------
+
+struct BatchGroup {
+    int np[3] = {1, 1, 1};
+    std::vector<int> inst;            // instance indices
+    TileShape tile[3];                // per direction
+    size_t oargs[2] = {0, 0}, ostart[2] = {0, 0};   // descriptor offsets (bytes into the workspace)
+    size_t xargs = 0, xstart = 0;
+    long otiles[2] = {0, 0}, xtiles = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+};
+
+struct Batch {
+    std::vector<Plan> plans;
+    std::vector<size_t> base;         // workspace offset of each instance's region
+    std::vector<int> powner[3];       // instance whose P table instance i uses, per direction
+    std::vector<BatchGroup> groups;
+    int dim = 0, nc = 0, precision = 0;
+    size_t desc = 0, desc_bytes = 0, total = 0;
+    char* uploaded = nullptr;         // the workspace the descriptors point into
+    hipEvent_t fork = nullptr;
+    // Bumped whenever the descriptors change shape or address; a graph
+    // captured before then refuses to launch.  Shared with the graphs so that
+    // it outlives the batch (0 = batch destroyed).
+    std::shared_ptr<unsigned> generation = std::make_shared<unsigned>(1);
+};
+
+size_t desc_bytes_of(const Batch& B) {
+    size_t n = 0;
+    for (const BatchGroup& G : B.groups) {
+        const size_t k = G.inst.size();
+        n += size_t(B.dim - 1) * a256(k * sizeof(OuterArgs)) + size_t(B.dim - 1) * a256((k + 1) * sizeof(long));
+        n += a256(k * sizeof(XArgs)) + a256((k + 1) * sizeof(long));
+    }
+    return n;
+}
+
+etd_status batch_layout(Batch& B) {
+    size_t off = 0;
+    B.base.resize(B.plans.size());
+    for (size_t i = 0; i < B.plans.size(); ++i) {
+        B.base[i] = off;
+        off = a256(off + B.plans[i].lay.total);
+    }
+    for (int d = 0; d < 3; ++d) {
+        B.powner[d].assign(B.plans.size(), 0);
+        for (size_t i = 0; i < B.plans.size(); ++i) {
+            size_t j = 0;
+            while (j < i && !(B.plans[j].n[d] == B.plans[i].n[d] && B.plans[j].np[d] == B.plans[i].np[d])) ++j;
+            B.powner[d][i] = int(j);
+        }
+    }
+    for (size_t i = 0; i < B.plans.size(); ++i) {
+        const Plan& pl = B.plans[i];
+        size_t g = 0;
+        while (g < B.groups.size() &&
+               !(B.groups[g].np[0] == pl.np[0] && B.groups[g].np[1] == pl.np[1] && B.groups[g].np[2] == pl.np[2]))
+            ++g;
+        if (g == B.groups.size()) {
+            BatchGroup G;
+            for (int d = 0; d < 3; ++d) G.np[d] = pl.np[d];
+            B.groups.push_back(G);
+        }
+        B.groups[g].inst.push_back(int(i));
+    }
+    B.desc = off;
+    B.desc_bytes = desc_bytes_of(B);
+    B.total = a256(off + B.desc_bytes);
+    return ETD_OK;
+}
+
+// Host image of one group's descriptors for the workspace at ws, with the
+// group's current tile shapes.
+void group_descriptors(const Batch& B, BatchGroup& G, char* ws, size_t& off, std::vector<uint8_t>& img) {
+    const int k = int(G.inst.size());
+    std::vector<OuterArgs> oa[2];
+    std::vector<long> os[2];
+    std::vector<XArgs> xa;
+    std::vector<long> xs;
+    for (int j = 0; j < 2; ++j) os[j].push_back(0);
+    xs.push_back(0);
+    for (int i : G.inst) {
+        const Plan& pl = B.plans[i];
+        const void* Pdir[3];
+        for (int d = 0; d < 3; ++d) {
+            const int o = B.powner[d][i];
+            Pdir[d] = ws + B.base[o] + B.plans[o].lay.P[d];
+        }
+        StepArgs a = step_args(pl, ws + B.base[i], Pdir);
+        for (int j = 0; j < a.nouter; ++j) {
+            const TileShape t = G.tile[a.odir[j]];
+            a.outer[j].rxn = rxn_args(pl, ws + B.base[i], 0.0);
+            a.outer[j].ncb /= t.cb;
+            oa[j].push_back(a.outer[j]);
+            os[j].push_back(os[j].back() + a.ocols[j] / t.cb);
+        }
+        a.x.rxn = rxn_args(pl, ws + B.base[i], 0.0);
+        xa.push_back(a.x);
+        xs.push_back(xs.back() + a.nlines / (16 * G.tile[0].cb));
+    }
+    auto put_bytes = [&](const void* src, size_t n) {
+        const size_t at = off;
+        std::memcpy(img.data() + (at - B.desc), src, n);
+        off = a256(off + n);
+        return at;
+    };
+    for (int j = 0; j < B.dim - 1; ++j) {
+        G.oargs[j] = put_bytes(oa[j].data(), k * sizeof(OuterArgs));
+        G.ostart[j] = put_bytes(os[j].data(), (k + 1) * sizeof(long));
+        G.otiles[j] = os[j].back();
+    }
+    G.xargs = put_bytes(xa.data(), k * sizeof(XArgs));
+    G.xstart = put_bytes(xs.data(), (k + 1) * sizeof(long));
+    G.xtiles = xs.back();
+}
+
+// Rebuild and upload every group's descriptors (synchronous on s).
+etd_status upload_descriptors(Batch& B, char* ws, hipStream_t s) {
+    std::vector<uint8_t> img(B.desc_bytes, 0);
+    size_t off = B.desc;
+    for (BatchGroup& G : B.groups) group_descriptors(B, G, ws, off, img);
+    HIP_TRY(hipMemcpyAsync(ws + B.desc, img.data(), img.size(), hipMemcpyHostToDevice, s), "descriptor upload");
+    HIP_TRY(hipStreamSynchronize(s), "descriptor upload sync");
+    B.uploaded = ws;
+    ++*B.generation;
+    return ETD_OK;
+}
+
+// One stage of one step for every instance of a group: stage 0 = first outer
+// stage, 1 = middle outer stage (3-D), 2 = x stage.
+template <typename M, int NC>
+etd_status group_stage(const Batch& B, const BatchGroup& G, int stage, char* ws, double t0, int k, hipStream_t s) {
+    typedef typename M::elem T;
+    const int n = int(G.inst.size());
+    if (stage < 2) {
+        const int d = B.dim == 3 ? (stage == 0 ? 2 : 1) : 1;
+        const int NP = G.np[d];
+        Group<OuterArgs> g{reinterpret_cast<const OuterArgs*>(ws + G.oargs[stage]),
+                           reinterpret_cast<const long*>(ws + G.ostart[stage]), n, G.otiles[stage], t0, k};
+        if (stage == 0)
+            return outer_by_shape<T, NC>(NP, G.tile[d], [&](auto rb, auto cb, auto mt) {
+                return launch_outer_group_k<M, NC, true, decltype(rb)::value, decltype(cb)::value,
+                                            decltype(mt)::value>(g, NP, s);
+            });
+        return outer_by_shape<T, NC>(NP, G.tile[d], [&](auto rb, auto cb, auto mt) {
+            return launch_outer_group_k<M, NC, false, decltype(rb)::value, decltype(cb)::value, decltype(mt)::value>(
+                g, NP, s);
+        });
+    }
+    Group<XArgs> g{reinterpret_cast<const XArgs*>(ws + G.xargs), reinterpret_cast<const long*>(ws + G.xstart), n,
+                   G.xtiles, t0, k};
+    return x_by_shape<T, NC>(G.np[0], G.tile[0], [&](auto rb, auto cb, auto mt) {
+        return launch_x_group_k<M, NC, decltype(rb)::value, decltype(cb)::value, decltype(mt)::value>(g, G.np[0], s);
+    });
+}
+
+template <typename M, int NC>
+etd_status batch_advance_t(Batch& B, void* const* u, double t0, int nsteps, char* ws, hipStream_t s) {
+    typedef typename M::elem T;
+    const bool fork = B.groups.size() > 1;
+    if (fork) HIP_TRY(hipEventRecord(B.fork, s), "batch fork record");
+    for (BatchGroup& G : B.groups) {
+        hipStream_t gs = fork ? G.stream : s;
+        if (fork) HIP_TRY(hipStreamWaitEvent(gs, B.fork, 0), "batch fork wait");
+        for (int i : G.inst) {
+            const Plan& pl = B.plans[i];
+            hipLaunchKernelGGL(pack_field<T>, dim3(1024), dim3(256), 0, gs, static_cast<const T*>(u[i]),
+                               reinterpret_cast<T*>(ws + B.base[i] + pl.lay.field[0]), dims_of(pl));
+        }
+        HIP_TRY(hipGetLastError(), "batch pack launch");
+        for (int step = 0; step < nsteps; ++step) {
+            for (int stage = 0; stage < B.dim - 1; ++stage) TRY((group_stage<M, NC>(B, G, stage, ws, t0, step, gs)));
+            TRY((group_stage<M, NC>(B, G, 2, ws, t0, step + 1, gs)));
+        }
+        for (int i : G.inst) {
+            const Plan& pl = B.plans[i];
+            hipLaunchKernelGGL(unpack_field<T>, dim3(1024), dim3(256), 0, gs,
+                               reinterpret_cast<const T*>(ws + B.base[i] + pl.lay.field[0]), static_cast<T*>(u[i]),
+                               dims_of(pl));
+        }
+        HIP_TRY(hipGetLastError(), "batch unpack launch");
+        if (fork) {
+            HIP_TRY(hipEventRecord(G.done, gs), "batch join record");
+            HIP_TRY(hipStreamWaitEvent(s, G.done, 0), "batch join wait");
+        }
+    }
+    return ETD_OK;
+}
+
+template <typename M, int NC>
+etd_status batch_autotune_t(Batch& B, char* ws, hipStream_t s) {
+    typedef typename M::elem T;
+    for (BatchGroup& G : B.groups) {
+        const long nlines = long(G.np[1]) * G.np[2];
+        for (int stage = 0; stage < B.dim; ++stage) {
+            const int d = stage == B.dim - 1 ? 0 : (B.dim == 3 ? (stage == 0 ? 2 : 1) : 1);
+            const int st_kind = stage == B.dim - 1 ? 2 : stage;
+            const std::vector<TileShape> cand =
+                d == 0 ? x_candidates<T, NC>(G.np[0], nlines) : outer_candidates<T, NC>(G.np[d]);
+            TileShape best{};
+            float best_ms = 0.f;
+            for (TileShape t : cand) {
+                G.tile[d] = t;
+                TRY(upload_descriptors(B, ws, s));
+                float ms = 0.f;
+                TRY(time_launches([&]() { return group_stage<M, NC>(B, G, st_kind, ws, 0.0, 0, s); }, kTuneReps, s, ms));
+                if (best.rb == 0 || ms < best_ms) {
+                    best = t;
+                    best_ms = ms;
+                }
+            }
+            G.tile[d] = best;
+        }
+    }
+    return upload_descriptors(B, ws, s);
+}
+
+// ---------------------------------------------------------------------------
+// HIP graphs: the launches of a call captured once and replayed.
+// ---------------------------------------------------------------------------
+
+etd_status end_capture(hipStream_t s, etd_status st, hipGraph_t& g) {
+    g = nullptr;
+    const hipError_t he = hipStreamEndCapture(s, &g);
+    if (st != ETD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        g = nullptr;
+        return st;
+    }
+    if (he != hipSuccess) return hip_fail(he, "graph capture");
+    return ETD_OK;
+}
+
+}  // namespace
+
+struct etd_batch {
+    Batch b;
+};
+
+struct etd_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::shared_ptr<unsigned> generation;   // batch graphs: the batch's token
+    unsigned captured = 0;                  // its value at capture
+};
+
+namespace {
+
+etd_status batch_dispatch_advance(Batch& B, void* const* u, double t0, int nsteps, char* ws, hipStream_t s) {
+    switch (B.precision) {
+    case ETD_FP64:
+        return B.nc == 1 ? batch_advance_t<NativeMma<double>, 1>(B, u, t0, nsteps, ws, s)
+                         : batch_advance_t<NativeMma<double>, 2>(B, u, t0, nsteps, ws, s);
+    case ETD_FP32:
+        return B.nc == 1 ? batch_advance_t<NativeMma<float>, 1>(B, u, t0, nsteps, ws, s)
+                         : batch_advance_t<NativeMma<float>, 2>(B, u, t0, nsteps, ws, s);
+    default:
+        return B.nc == 1 ? batch_advance_t<Bf16x6Mma, 1>(B, u, t0, nsteps, ws, s)
+                         : batch_advance_t<Bf16x6Mma, 2>(B, u, t0, nsteps, ws, s);
+    }
+}
+
+etd_status batch_check(const Batch& B, void* const* u, int nsteps, const void* ws) {
+    if (!u) return fail(ETD_EINVAL, "field pointer array is NULL");
+    for (size_t i = 0; i < B.plans.size(); ++i)
+        if (!u[i]) return fail(ETD_EINVAL, "a field pointer is NULL");
+    if (nsteps < 0) return fail(ETD_EINVAL, "nsteps must be >= 0");
+    if (!ws || ws != B.uploaded) return fail(ETD_EWORKSPACE, "workspace is not the one the batch was uploaded to");
+    return ETD_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -2085,6 +2723,288 @@ etd_status etd_adjoint(const etd_plan* plan, const void* u0, double t0, int nste
         return pl.nc == 1 ? adjoint_t<Bf16x6Mma, 1>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s)
                           : adjoint_t<Bf16x6Mma, 2>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s);
     }
+}
+
+etd_status etd_plan_autotune(etd_plan* plan, void* ws, void* stream) {
+    if (!plan) return fail(ETD_EINVAL, "NULL plan");
+    etd_status st = check_ws(plan->p, ws);
+    if (st != ETD_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    Plan& pl = plan->p;
+    const bool timing = plan->timer.on;
+    plan->timer.on = false;
+    switch (pl.prob.precision) {
+    case ETD_FP64:
+        st = pl.nc == 1 ? autotune_plan_t<NativeMma<double>, 1>(pl, w, s) : autotune_plan_t<NativeMma<double>, 2>(pl, w, s);
+        break;
+    case ETD_FP32:
+        st = pl.nc == 1 ? autotune_plan_t<NativeMma<float>, 1>(pl, w, s) : autotune_plan_t<NativeMma<float>, 2>(pl, w, s);
+        break;
+    default:
+        st = pl.nc == 1 ? autotune_plan_t<Bf16x6Mma, 1>(pl, w, s) : autotune_plan_t<Bf16x6Mma, 2>(pl, w, s);
+    }
+    plan->timer.on = timing;
+    return st;
+}
+
+etd_status etd_plan_tiles(const etd_plan* plan, int tiles[6]) {
+    if (!plan || !tiles) return fail(ETD_EINVAL, "NULL argument");
+    const Plan& pl = plan->p;
+    for (int d = 0; d < 3; ++d) {
+        TileShape t{};
+        if (d < pl.dim) {
+            const etd_status st = resolve_tile_any(pl, d, TileShape{pl.tile_rb[d], pl.tile_cb[d]}, t);
+            if (st != ETD_OK) return st;
+        }
+        tiles[2 * d] = t.rb;
+        tiles[2 * d + 1] = t.cb;
+    }
+    return ETD_OK;
+}
+
+etd_status etd_plan_set_tiles(etd_plan* plan, const int tiles[6]) {
+    if (!plan || !tiles) return fail(ETD_EINVAL, "NULL argument");
+    Plan& pl = plan->p;
+    TileShape r[3];
+    for (int d = 0; d < pl.dim; ++d) {
+        const etd_status st = resolve_tile_any(pl, d, TileShape{tiles[2 * d], tiles[2 * d + 1]}, r[d]);
+        if (st != ETD_OK) return st;
+    }
+    for (int d = 0; d < pl.dim; ++d) {
+        const bool dflt = tiles[2 * d] == 0 && tiles[2 * d + 1] == 0;
+        pl.tile_rb[d] = dflt ? 0 : r[d].rb;
+        pl.tile_cb[d] = dflt ? 0 : r[d].cb;
+    }
+    return ETD_OK;
+}
+
+etd_status etd_batch_create(const etd_problem* probs, int count, etd_batch** out) {
+    if (!probs || !out) return fail(ETD_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (count < 1 || count > kMaxBatch) return fail(ETD_EINVAL, "count must be in 1..4096");
+    etd_batch* b = new (std::nothrow) etd_batch;
+    if (!b) return fail(ETD_EINVAL, "out of host memory");
+    Batch& B = b->b;
+    B.plans.resize(count);
+    for (int i = 0; i < count; ++i) {
+        std::string err;
+        const etd_status st = build_plan(probs[i], B.plans[i], err);
+        if (st != ETD_OK) {
+            delete b;
+            return fail(st, "instance " + std::to_string(i) + ": " + err);
+        }
+        const Plan& pl = B.plans[i];
+        if (i == 0) {
+            B.dim = pl.dim;
+            B.nc = pl.nc;
+            B.precision = pl.prob.precision;
+        } else if (pl.dim != B.dim || pl.nc != B.nc || pl.prob.precision != B.precision) {
+            delete b;
+            return fail(ETD_EINVAL, "instance " + std::to_string(i) +
+                                        ": a batch takes one dimension, component count and precision");
+        }
+        bool fused = x_fused(pl.np[0], pl.nc, pl.elem);
+        for (int d = 1; d < pl.dim; ++d) fused = fused && outer_fused(pl.np[d], pl.nc, pl.elem);
+        if (!fused) {
+            delete b;
+            return fail(ETD_EUNSUPPORTED, "instance " + std::to_string(i) +
+                                              ": its two-component tile exceeds the LDS (single plans only)");
+        }
+    }
+    batch_layout(B);
+    for (BatchGroup& G : B.groups) {
+        const Plan& pl = B.plans[G.inst[0]];
+        for (int d = 0; d < pl.dim; ++d) {
+            const etd_status st = resolve_tile_any(pl, d, TileShape{}, G.tile[d]);
+            if (st != ETD_OK) {
+                delete b;
+                return st;
+            }
+        }
+    }
+    *out = b;
+    return ETD_OK;
+}
+
+etd_status etd_batch_workspace_bytes(const etd_batch* batch, size_t* bytes) {
+    if (!batch || !bytes) return fail(ETD_EINVAL, "NULL argument");
+    *bytes = batch->b.total;
+    return ETD_OK;
+}
+
+etd_status etd_batch_upload(etd_batch* batch, void* ws, size_t bytes, void* stream) {
+    if (!batch) return fail(ETD_EINVAL, "NULL batch");
+    Batch& B = batch->b;
+    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(ETD_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+    if (bytes < B.total) return fail(ETD_EWORKSPACE, "workspace smaller than etd_batch_workspace_bytes()");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    for (size_t i = 0; i < B.plans.size(); ++i) {
+        const Plan& pl = B.plans[i];
+        HIP_TRY(hipMemcpyAsync(w + B.base[i], pl.image.data(), pl.table_bytes, hipMemcpyHostToDevice, s),
+                "table upload");
+        HIP_TRY(hipMemsetAsync(w + B.base[i] + pl.lay.field[0], 0, pl.lay.total - pl.lay.field[0], s),
+                "workspace clear");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "table upload sync");
+    if (!B.fork) HIP_TRY(hipEventCreateWithFlags(&B.fork, hipEventDisableTiming), "batch event");
+    for (BatchGroup& G : B.groups) {
+        if (!G.stream) HIP_TRY(hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking), "batch stream");
+        if (!G.done) HIP_TRY(hipEventCreateWithFlags(&G.done, hipEventDisableTiming), "batch event");
+    }
+    return upload_descriptors(B, w, s);
+}
+
+etd_status etd_batch_advance(etd_batch* batch, void* const* u, double t0, int nsteps, void* ws, void* stream) {
+    if (!batch) return fail(ETD_EINVAL, "NULL batch");
+    if (!std::isfinite(t0)) return fail(ETD_EINVAL, "t0 must be finite");
+    Batch& B = batch->b;
+    etd_status st = batch_check(B, u, nsteps, ws);
+    if (st != ETD_OK) return st;
+    if (nsteps == 0) return ETD_OK;
+    return batch_dispatch_advance(B, u, t0, nsteps, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+}
+
+etd_status etd_batch_autotune(etd_batch* batch, void* ws, void* stream) {
+    if (!batch) return fail(ETD_EINVAL, "NULL batch");
+    Batch& B = batch->b;
+    if (!ws || ws != B.uploaded) return fail(ETD_EWORKSPACE, "workspace is not the one the batch was uploaded to");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    switch (B.precision) {
+    case ETD_FP64:
+        return B.nc == 1 ? batch_autotune_t<NativeMma<double>, 1>(B, w, s) : batch_autotune_t<NativeMma<double>, 2>(B, w, s);
+    case ETD_FP32:
+        return B.nc == 1 ? batch_autotune_t<NativeMma<float>, 1>(B, w, s) : batch_autotune_t<NativeMma<float>, 2>(B, w, s);
+    default:
+        return B.nc == 1 ? batch_autotune_t<Bf16x6Mma, 1>(B, w, s) : batch_autotune_t<Bf16x6Mma, 2>(B, w, s);
+    }
+}
+
+etd_status etd_batch_tiles(const etd_batch* batch, int instance, int tiles[6]) {
+    if (!batch || !tiles) return fail(ETD_EINVAL, "NULL argument");
+    const Batch& B = batch->b;
+    if (instance < 0 || instance >= int(B.plans.size())) return fail(ETD_EINVAL, "instance out of range");
+    for (const BatchGroup& G : B.groups)
+        for (int i : G.inst)
+            if (i == instance) {
+                for (int d = 0; d < 3; ++d) {
+                    tiles[2 * d] = d < B.dim ? G.tile[d].rb : 0;
+                    tiles[2 * d + 1] = d < B.dim ? G.tile[d].cb : 0;
+                }
+                return ETD_OK;
+            }
+    return fail(ETD_EINVAL, "instance not found");
+}
+
+etd_status etd_batch_groups(const etd_batch* batch, int* groups) {
+    if (!batch || !groups) return fail(ETD_EINVAL, "NULL argument");
+    *groups = int(batch->b.groups.size());
+    return ETD_OK;
+}
+
+etd_status etd_batch_destroy(etd_batch* batch) {
+    if (!batch) return ETD_OK;
+    Batch& B = batch->b;
+    for (BatchGroup& G : B.groups) {
+        if (G.stream) (void)hipStreamDestroy(G.stream);
+        if (G.done) (void)hipEventDestroy(G.done);
+    }
+    if (B.fork) (void)hipEventDestroy(B.fork);
+    *B.generation = 0;
+    delete batch;
+    return ETD_OK;
+}
+
+etd_status etd_graph_capture(const etd_plan* plan, void* u, double t0, int nsteps, void* ws, void* stream,
+                             etd_graph** out) {
+    if (!plan || !out || !u) return fail(ETD_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (!stream) return fail(ETD_EINVAL, "graph capture needs a stream other than the default stream");
+    if (nsteps < 1) return fail(ETD_EINVAL, "nsteps must be >= 1");
+    if (!std::isfinite(t0)) return fail(ETD_EINVAL, "t0 must be finite");
+    etd_status st = check_ws(plan->p, ws);
+    if (st != ETD_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool timing = plan->timer.on;
+    plan->timer.on = false;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "graph capture begin");
+    char* w = static_cast<char*>(ws);
+    switch (plan->p.prob.precision) {
+    case ETD_FP64: st = advance_m<NativeMma<double>>(plan->p, plan->timer, u, t0, nsteps, w, s); break;
+    case ETD_FP32: st = advance_m<NativeMma<float>>(plan->p, plan->timer, u, t0, nsteps, w, s); break;
+    default: st = advance_m<Bf16x6Mma>(plan->p, plan->timer, u, t0, nsteps, w, s);
+    }
+    plan->timer.on = timing;
+    hipGraph_t g;
+    st = end_capture(s, st, g);
+    if (st != ETD_OK) return st;
+    etd_graph* G = new (std::nothrow) etd_graph;
+    if (!G) {
+        (void)hipGraphDestroy(g);
+        return fail(ETD_EINVAL, "out of host memory");
+    }
+    G->graph = g;
+    const hipError_t he = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+    if (he != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        delete G;
+        return hip_fail(he, "graph instantiate");
+    }
+    *out = G;
+    return ETD_OK;
+}
+
+etd_status etd_batch_graph_capture(etd_batch* batch, void* const* u, double t0, int nsteps, void* ws, void* stream,
+                                   etd_graph** out) {
+    if (!batch || !out) return fail(ETD_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (!stream) return fail(ETD_EINVAL, "graph capture needs a stream other than the default stream");
+    if (nsteps < 1) return fail(ETD_EINVAL, "nsteps must be >= 1");
+    if (!std::isfinite(t0)) return fail(ETD_EINVAL, "t0 must be finite");
+    Batch& B = batch->b;
+    etd_status st = batch_check(B, u, nsteps, ws);
+    if (st != ETD_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "graph capture begin");
+    st = batch_dispatch_advance(B, u, t0, nsteps, static_cast<char*>(ws), s);
+    hipGraph_t g;
+    st = end_capture(s, st, g);
+    if (st != ETD_OK) return st;
+    etd_graph* G = new (std::nothrow) etd_graph;
+    if (!G) {
+        (void)hipGraphDestroy(g);
+        return fail(ETD_EINVAL, "out of host memory");
+    }
+    G->graph = g;
+    G->generation = B.generation;
+    G->captured = *B.generation;
+    const hipError_t he = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+    if (he != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        delete G;
+        return hip_fail(he, "graph instantiate");
+    }
+    *out = G;
+    return ETD_OK;
+}
+
+etd_status etd_graph_launch(etd_graph* graph, void* stream) {
+    if (!graph || !graph->exec) return fail(ETD_EINVAL, "NULL graph");
+    if (graph->generation && *graph->generation != graph->captured)
+        return fail(ETD_EINVAL, "graph is stale: its batch was re-tuned, re-uploaded or destroyed since capture");
+    HIP_TRY(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)), "graph launch");
+    return ETD_OK;
+}
+
+etd_status etd_graph_destroy(etd_graph* graph) {
+    if (!graph) return ETD_OK;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+    return ETD_OK;
 }
 
 etd_status etd_compare(const etd_plan* plan, const void* a, const void* b, double out[4], void* ws, void* stream) {

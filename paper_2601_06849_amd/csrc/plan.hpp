@@ -88,6 +88,10 @@ struct Plan {
     std::vector<uint8_t> image;             // host image of the table region
     size_t table_bytes = 0;                 // bytes of image (start of workspace)
     size_t diag_stride = 0;                 // elements between diag slots (max NP)
+    // stage tile shape per direction (rows per wave, column/line blocks);
+    // 0 = the built-in default, else set by the autotuner or the caller
+    int tile_rb[3] = {0, 0, 0};
+    int tile_cb[3] = {0, 0, 0};
 };
 
 etd_status build_plan(const etd_problem& p, Plan& out, std::string& err);

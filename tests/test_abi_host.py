@@ -201,3 +201,67 @@ def test_adjoint_workspace_query(etd):
         assert ei.value.status == etd.ETD_EUNSUPPORTED
     finally:
         etd.etd_plan_destroy(plan)
+
+
+def test_tile_shapes_host_validation(etd):
+    """Tile requests are validated on the host: default shapes are reported,
+    invalid ones rejected without changing the plan."""
+    p = W.Problem(dim=3, n=(255, 100, 1000), kappa=(0.1,), tau=0.01, reaction="fisher", precision="fp32")
+    plan = etd.etd_plan_create(p)
+    try:
+        d = etd.etd_plan_tiles(plan)
+        assert d == [(2, 4), (2, 2), (4, 1)]
+        etd.etd_plan_set_tiles(plan, [(4, 1), (2, 1), (4, 1)])
+        assert etd.etd_plan_tiles(plan) == [(4, 1), (2, 1), (4, 1)]
+        for bad in ([(2, 8)], [(3, 1)], [(2, 1), (2, 1), (2, 1)], [(2, 1), (2, 4)]):
+            with pytest.raises(etd.EtdError) as ei:
+                etd.etd_plan_set_tiles(plan, bad)
+            assert ei.value.status == etd.ETD_EUNSUPPORTED
+        assert etd.etd_plan_tiles(plan) == [(4, 1), (2, 1), (4, 1)]
+        etd.etd_plan_set_tiles(plan, [(0, 0)] * 3)
+        assert etd.etd_plan_tiles(plan) == d
+    finally:
+        etd.etd_plan_destroy(plan)
+    p64 = p.replace(n=(255, 96, 64), precision="fp64")
+    plan = etd.etd_plan_create(p64)
+    try:
+        assert etd.etd_plan_tiles(plan) == [(2, 2), (2, 1), (2, 1)]
+        with pytest.raises(etd.EtdError):   # rb = 4 at <= 8 waves is built for FP32 states only
+            etd.etd_plan_set_tiles(plan, [(4, 1)])
+    finally:
+        etd.etd_plan_destroy(plan)
+
+
+def test_batch_host_validation(etd):
+    """Batches: grouping by padded shape, shared limits and host-side errors."""
+    a = W.Problem(dim=2, n=(100, 100), kappa=(0.1,), tau=0.01, reaction="fisher")
+    probs = [a, a.replace(n=(97, 100), q=0.5), a.replace(n=(127, 100)),
+             a.replace(n=(100, 140), pade=4, reaction="allen_cahn")]
+    b = etd.etd_batch_create(probs)
+    try:
+        assert etd.etd_batch_groups(b) == 2          # 97, 100, 127 pad to 128; 140 to 160
+        assert etd.etd_batch_workspace_bytes(b) % 256 == 0
+        assert etd.etd_batch_tiles(b, 0) == etd.etd_batch_tiles(b, 1)
+        with pytest.raises(etd.EtdError):
+            etd.etd_batch_tiles(b, 4)
+        L = etd.lib()
+        ptrs = (ctypes.c_void_p * 4)(0x1000, 0x2000, 0x3000, 0x4000)
+        # not uploaded: every workspace is rejected before any device work
+        assert L.etd_batch_advance(b, ptrs, 0.0, 1, ctypes.c_void_p(0x10000), None) == etd.ETD_EWORKSPACE
+        ptrs[2] = None
+        assert L.etd_batch_advance(b, ptrs, 0.0, 1, ctypes.c_void_p(0x10000), None) == etd.ETD_EINVAL
+        h = ctypes.c_void_p()
+        assert L.etd_batch_graph_capture(b, ptrs, 0.0, 1, ctypes.c_void_p(0x10000), None, ctypes.byref(h)) == \
+            etd.ETD_EINVAL   # the null stream cannot be captured
+    finally:
+        etd.etd_batch_destroy(b)
+    for bad in ([a, a.replace(precision="fp32")], [a, a.replace(dim=3, n=(10, 10, 10))], []):
+        with pytest.raises((etd.EtdError, ValueError)) as ei:
+            etd.etd_batch_create(bad)
+    with pytest.raises(etd.EtdError) as ei:
+        etd.etd_batch_create([a, a.replace(tau=-1.0)])
+    assert "instance 1" in str(ei.value)
+    fhn = W.Problem(dim=2, n=(700, 32), kappa=(0.1, 0.1), tau=0.01, reaction="fhn_cubic", precision="fp32")
+    with pytest.raises(etd.EtdError) as ei:
+        etd.etd_batch_create([fhn])
+    assert ei.value.status == etd.ETD_EUNSUPPORTED

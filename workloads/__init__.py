@@ -240,6 +240,26 @@ def fhn3d(precision="fp32", n=127, nsteps=400) -> Workload:
     return Workload(f"fhn3d_n{n}", p, nsteps, "fhn_patch", SEED0 + 4)
 
 
+def batched2d(count: int = 256, extents=(127, 255, 511, 1023), nsteps: int = 100, precision: str = "fp32",
+              seed: int = SEED0 + 3):
+    """Many uneven 2-D Fisher-KPP instances advanced together: per instance,
+    drawn in this order from one generator, n ~ U{extents} (square grid),
+    kappa log-uniform on [1e-3, 1e-1], q ~ U[0, 1], then its initial field
+    (sine product plus U(-0.01, 0.01) noise, from a seed drawn here too);
+    tau = 0.01, f = u(1-u).  Returns (problems, u0 list, nsteps)."""
+    rng = np.random.default_rng(seed)
+    problems, u0s = [], []
+    for _ in range(count):
+        n = int(rng.choice(extents))
+        kappa = float(10.0 ** rng.uniform(-3.0, -1.0))
+        q = float(rng.uniform(0.0, 1.0))
+        init_seed = int(rng.integers(0, 2 ** 31 - 1))
+        p = Problem(dim=2, n=(n, n), kappa=(kappa,), q=q, tau=0.01, reaction="fisher", precision=precision)
+        problems.append(p)
+        u0s.append(u0_sine_noise(p, init_seed))
+    return problems, u0s, nsteps
+
+
 # Paper examples (Sec. 5), used as printed-value pins.  The paper's m counts
 # intervals, so m = 512 means 511 interior points and m = 80 means 79.
 

@@ -10,11 +10,14 @@ in FP64; the reduced-precision variant is timed beside it and its relative L2
 distance to the FP64 result is reported.
 
 Prints one JSON line.  Options: --steps K (timed steps), --warmup W,
---precision fp64|fp32|bf16x6, --reduced fp32,bf16x6|none, --cpu-steps S
-(oracle sample),
+--precision fp64|fp32|bf16x6, --reduced fp32,bf16x6|none, --cpu-steps S and
+--cpu-seconds T (oracle sample: chunks of S steps until T seconds),
 --no-cpu-baseline, --n (grid size per direction), --adjoint-steps N (the
 adjoint leg: one gradient of 1/2||u(T) - u_target||^2 through N steps of the
-3-D FitzHugh-Nagumo workload, 127^3, FP32; 0 skips it).
+3-D FitzHugh-Nagumo workload, 127^3, FP32; 0 skips it), --batched-steps N
+(256 uneven 2-D Fisher-KPP instances, n in {127, 255, 511, 1023}, FP32, in one
+batch: default tiles, autotuned tiles and a captured HIP graph; 0 skips it),
+--latency-steps N (the 63^2 Fisher-KPP case, eager calls vs a graph).
 """
 import argparse
 import hashlib
@@ -46,10 +49,13 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x6"])
     ap.add_argument("--reduced", default="fp32,bf16x6",
                     help="comma-separated reduced-precision variants timed beside fp64, or 'none'")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=255)
     ap.add_argument("--adjoint-steps", type=int, default=400)
+    ap.add_argument("--batched-steps", type=int, default=100)
+    ap.add_argument("--latency-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     return ap.parse_args()
@@ -154,6 +160,77 @@ def adjoint_leg(etd, torch, W, nsteps):
             "grad_kappa": grad[:p.ncomp], "grad_q": grad[p.ncomp]}
 
 
+def batched_leg(etd, torch, W, nsteps):
+    """Grouped persistent launches over the 256-instance uneven 2-D workload:
+    grid-point updates/s and useful FP32 TFLOP/s (18 n^3 per instance-step),
+    with the default tile shapes, with autotuned ones, and as a graph."""
+    problems, u0s, _ = W.batched2d(nsteps=nsteps)
+    b = etd.Batch(problems)
+    fields = b.fields(u0s)
+    updates = sum(p.npoints for p in problems) * nsteps
+    flops = sum(18.0 * p.n[0] ** 3 for p in problems) * nsteps
+    peak = PEAK_TFLOPS["fp32"]
+
+    def timed(run):
+        run(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(nsteps)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        return {"ms_per_step": 1e3 * sec / nsteps, "updates_per_s": updates / sec,
+                "useful_tflops": flops / sec / 1e12, "frac_of_fp32_peak": flops / sec / 1e12 / peak}
+
+    out = {"workload": "fisher2d_batched256", "instances": len(problems), "groups": b.groups(),
+           "extents": {str(n): sum(1 for p in problems if p.n[0] == n) for n in (127, 255, 511, 1023)},
+           "steps": nsteps, "precision": "fp32"}
+    out["default_tiles"] = timed(lambda k: b.advance(fields, k))
+    b.autotune()
+    out["autotuned_tiles"] = timed(lambda k: b.advance(fields, k))
+    out["autotuned_tiles"]["tiles"] = {str(p.n[0]): b.tiles(i)[:2] for i, p in
+                                       reversed(list(enumerate(problems)))}
+    s = torch.cuda.Stream()
+    graphs = {}
+
+    def graph_run(k):
+        if k not in graphs:
+            graphs[k] = b.capture(fields, k, s)
+        graphs[k].launch(s)
+        s.synchronize()
+    out["graph"] = timed(graph_run)
+    for g in graphs.values():
+        g.close()
+    b.close()
+    return out
+
+
+def latency_leg(etd, torch, W, nsteps):
+    """The 63^2 Fisher-KPP case, where a step is a few microseconds of work:
+    eager etd_advance calls of one step each vs one captured graph."""
+    wl = W.fisher2d_small()
+    st = etd.Stepper(wl.problem)
+    u = st.field(wl.u0())
+    st.advance(u, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        st.advance(u, 1)
+    torch.cuda.synchronize()
+    eager = time.perf_counter() - t0
+    s = torch.cuda.Stream()
+    g = st.capture(u, nsteps, s)
+    g.launch(s)
+    s.synchronize()
+    t0 = time.perf_counter()
+    g.launch(s)
+    s.synchronize()
+    graph = time.perf_counter() - t0
+    g.close()
+    st.close()
+    return {"workload": wl.name, "steps": nsteps, "eager_us_per_step": 1e6 * eager / nsteps,
+            "graph_us_per_step": 1e6 * graph / nsteps}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -218,19 +295,28 @@ def main():
 
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint_leg(etd, torch, W, args.adjoint_steps)
+    if args.batched_steps > 0:
+        out["batched"] = batched_leg(etd, torch, W, args.batched_steps)
+    if args.latency_steps > 0:
+        out["latency"] = latency_leg(etd, torch, W, args.latency_steps)
 
     if not args.no_cpu_baseline:
+        # the oracle as it stands, in chunks of --cpu-steps steps until about
+        # --cpu-seconds of host time have been spent (bounded sample)
         import oracle
         p = wl.problem.replace(precision="fp64")
-        u0 = wl.u0()
+        u = wl.u0()
         cores = oracle.threads(0)
-        t0 = time.perf_counter()
-        oracle.advance(p, u0, args.cpu_steps, nthreads=0)
-        cs = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": npts * args.cpu_steps / cs, "unit": "grid-point updates/s", "cores": cores,
+        done, cs = 0, 0.0
+        while cs < args.cpu_seconds and done < 400:
+            t0 = time.perf_counter()
+            u = oracle.advance(p, u, args.cpu_steps, t0=done * p.tau, nthreads=0)
+            cs += time.perf_counter() - t0
+            done += args.cpu_steps
+        out["cpu_baseline"] = {"value": npts * done / cs, "unit": "grid-point updates/s", "cores": cores,
                                "kind": "oracle",
-                               "sample": f"{args.cpu_steps} steps of {wl.name} from the same u0 "
-                                         f"({cs:.1f} s, FP64 complex Thomas line solves)"}
+                               "sample": f"first {done} steps of {wl.name} from the same u0 in {cs:.1f} s "
+                                         f"(FP64 complex Thomas line solves, OpenMP over lines)"}
     print(json.dumps(out), flush=True)
 
 

@@ -107,7 +107,13 @@ def _ptr(a: np.ndarray):
 def advance(p, u: np.ndarray, nsteps: int, t0: float = 0.0, nthreads: int = 0,
             precision: str = "fp64") -> np.ndarray:
     """Return U after nsteps steps of the scheme from time t0 (input untouched).
-    precision="extended" runs the referee build (x87 extended arithmetic)."""
+    precision="extended" runs the referee build (x87 extended arithmetic).
+    pade = 0 selects the exact-exponential scheme (``oracle.phi``, FP64)."""
+    if p.pade == 0:
+        if precision != "fp64":
+            raise ValueError("the exact-exponential oracle runs in FP64 only")
+        from . import phi
+        return phi.advance(p, u, nsteps, t0)
     out = _f64(u, p.shape).copy()
     rc = lib(precision).etdo_advance(ctypes.byref(_struct(p)), _ptr(out), float(t0), int(nsteps), int(nthreads))
     if rc != 0:

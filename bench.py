@@ -17,7 +17,9 @@ adjoint leg: one gradient of 1/2||u(T) - u_target||^2 through N steps of the
 3-D FitzHugh-Nagumo workload, 127^3, FP32; 0 skips it), --batched-steps N
 (256 uneven 2-D Fisher-KPP instances, n in {127, 255, 511, 1023}, FP32, in one
 batch: default tiles, autotuned tiles and a captured HIP graph; 0 skips it),
---latency-steps N (the 63^2 Fisher-KPP case, eager calls vs a graph).
+--latency-steps N (the 63^2 Fisher-KPP case, eager calls vs a graph),
+--exact-steps N (the headline workload with the exact-exponential factors
+e^{-z}, phi_1, phi_2 in place of the Pade ones, FP64).
 """
 import argparse
 import hashlib
@@ -56,6 +58,7 @@ def parse():
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--latency-steps", type=int, default=100)
+    ap.add_argument("--exact-steps", type=int, default=50)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     return ap.parse_args()
@@ -299,6 +302,16 @@ def main():
         out["batched"] = batched_leg(etd, torch, W, args.batched_steps)
     if args.latency_steps > 0:
         out["latency"] = latency_leg(etd, torch, W, args.latency_steps)
+    if args.exact_steps > 0 and args.precision == "fp64":
+        # same kernels, exact-exponential diagonals; compared with the Pade
+        # result after the same steps from the same u0
+        wl_e = W.fisher3d(precision="fp64", n=args.n, nsteps=args.exact_steps)
+        u_e, sec_e, _, _ = timed_run(etd, torch, W.Workload(wl_e.name, wl_e.problem.replace(pade=0), wl_e.nsteps,
+                                                            wl_e.init, wl_e.seed), "fp64", args.exact_steps, 2)
+        u_p, _, _, _ = timed_run(etd, torch, wl_e, "fp64", args.exact_steps, 0)
+        out["exact_exponential"] = {"ms_per_step": 1e3 * sec_e / args.exact_steps,
+                                    "value": npts * args.exact_steps / sec_e, "steps": args.exact_steps,
+                                    "rel_l2_vs_pade02": float((u_e - u_p).norm() / u_p.norm())}
 
     if not args.no_cpu_baseline:
         # the oracle as it stands, in chunks of --cpu-steps steps until about

@@ -77,7 +77,9 @@ typedef struct {
     double tau;            /* time step > 0; T = nsteps*tau (Sec. 2.2) */
     int rxn;               /* etd_reaction */
     double rxn_param[8];
-    int pade;              /* 2: P_{0,2} family (Sec. 3.1); 4: P_{0,4} family (Sec. 5) */
+    int pade;              /* 2: P_{0,2} family (Sec. 3.1); 4: P_{0,4} family (Sec. 5);
+                              0: exact exponentials, Q_1..Q_3 = e^{-z}, phi_1, phi_2
+                              (the fully discrete scheme of Sec. 2.2) */
     int precision;         /* etd_precision */
 } etd_problem;
 
@@ -118,7 +120,8 @@ etd_status etd_compare(const etd_plan* plan, const void* a_dev, const void* b_de
 /* Host copies of the plan's FP64 tables, for inspection and tests (no device
  * involvement).  which: 0 = eigenvalues lambda_j of A_d (component comp),
  * 1 = eigenvector matrix P_d (n_d x n_d, row-major), 2/3/4 = the rational
- * factors Q_1, Q_2, Q_3 (or R_1..R_3) at tau*lambda_j.  count is the capacity
+ * factors Q_1, Q_2, Q_3 (R_1..R_3, or e^{-z}, phi_1, phi_2) at tau*lambda_j, 5/6/7 = the
+ * increments Q_1 - 1, Q_2 - 1, Q_3 - 1/2 the kernels apply.  count is the capacity
  * of out in doubles; ETD_EINVAL if too small. */
 etd_status etd_plan_table(const etd_plan* plan, int which, int d, int comp, double* out, size_t count);
 

@@ -404,44 +404,67 @@ __device__ __forceinline__ T react_coupled(const RxnArgs& r, int comp, T mine, T
 // of T (the contracted index contiguous, so a lane's B fragment is one
 // vector read), first the inputs (and f of them), then the scaled spectral
 // coefficients.
+// One thread's share of an outer tile's global inputs: ITER 16-byte vectors
+// of each loaded array (the workgroup has exactly 4 NP / RB threads).
 template <typename M, int NC, bool FIRST, int RB, int CB>
-__device__ __forceinline__ void outer_tile(const OuterArgs& a, long tile) {
+struct OuterRegs {
+    typedef typename Vec16<typename M::elem>::type TV;
+    static constexpr int ITER = 4 * RB * CB / Vec16<typename M::elem>::n;
+    static constexpr int NLOAD = FIRST ? NC : 2 * NC;
+    TV v[ITER][NLOAD];
+    TV other[(FIRST && NC == 1) ? ITER : 1];
+};
+
+template <typename M, int NC, bool FIRST, int RB, int CB>
+__device__ __forceinline__ void outer_load(const OuterArgs& a, long tile, OuterRegs<M, NC, FIRST, RB, CB>& g) {
     typedef typename M::elem T;
-    typedef typename Vec4<T>::type T4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
-    constexpr int NCOL = 16 * CB;         // columns per tile
-    constexpr int VPR = NCOL / VN;        // 16-byte global vectors per tile row
-    constexpr int NA = 2 * NC;
-    constexpr int NQ = NA * CB;           // B fragments per K block
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* X = reinterpret_cast<T*>(smem_raw);
-
-    const int NP = a.NP;
-    const int RS = NP + kInnerRowPad;     // LDS stride between columns
-    const int AST = NCOL * RS;
-    const int tid = threadIdx.x;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int lane = tid & 63;
-    const int li = lane & 15, lg = lane >> 4;
-    const int cb = int(tile % a.ncb);
-    const long bt = tile / a.ncb;
-    const long gbase = bt * a.sb + long(cb) * NCOL;
+    constexpr int NCOL = 16 * CB;
+    constexpr int VPR = NCOL / VN;
+    const int nvec = a.NP * VPR;
+    const long gbase = (tile / a.ncb) * a.sb + long(tile % a.ncb) * NCOL;
     const T* __restrict__ in0 = static_cast<const T*>(a.in0);
     const T* __restrict__ in1 = static_cast<const T*>(a.in1);
-    const void* __restrict__ P = a.P;
-
-    // ---- stage the tile (and the reaction, for the first stage) ----
-    const int nvec = NP * VPR;
-#pragma unroll 4
-    for (int v = tid; v < nvec; v += blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < OuterRegs<M, NC, FIRST, RB, CB>::ITER; ++i) {
+        const int v = threadIdx.x + i * blockDim.x;
+        if (v >= nvec) break;
         const int k = v / VPR, j0 = (v - k * VPR) * VN;
         const long gi = gbase + long(k) * a.sk + j0;
-        if constexpr (FIRST) {
-            TV u[NC], f[NC], other;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) u[c] = *reinterpret_cast<const TV*>(in0 + gi + c * a.sc);
-            if (NC == 1 && a.other) other = *reinterpret_cast<const TV*>(static_cast<const T*>(a.other) + gi);
+        for (int c = 0; c < NC; ++c) {
+            g.v[i][c] = *reinterpret_cast<const TV*>(in0 + gi + c * a.sc);
+            if constexpr (!FIRST) g.v[i][NC + c] = *reinterpret_cast<const TV*>(in1 + gi + c * a.sc);
+        }
+        if constexpr (FIRST && NC == 1)
+            if (a.other) g.other[i] = *reinterpret_cast<const TV*>(static_cast<const T*>(a.other) + gi);
+    }
+}
+
+// Registers -> LDS (and, in the first stage, f of them).  LDS: [2*NC
+// arrays][16*CB columns][NP + pad], the contracted index contiguous.
+template <typename M, int NC, bool FIRST, int RB, int CB>
+__device__ __forceinline__ void outer_store(const OuterArgs& a, long tile, const OuterRegs<M, NC, FIRST, RB, CB>& g) {
+    typedef typename M::elem T;
+    typedef typename Vec16<T>::type TV;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int NCOL = 16 * CB;
+    constexpr int VPR = NCOL / VN;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* X = reinterpret_cast<T*>(smem_raw);
+    const int NP = a.NP;
+    const int RS = NP + 16 / int(sizeof(T));
+    const int AST = NCOL * RS;
+    const int nvec = NP * VPR;
+    const int cb = int(tile % a.ncb);
+#pragma unroll
+    for (int i = 0; i < OuterRegs<M, NC, FIRST, RB, CB>::ITER; ++i) {
+        const int v = threadIdx.x + i * blockDim.x;
+        if (v >= nvec) break;
+        const int k = v / VPR, j0 = (v - k * VPR) * VN;
+        if constexpr (FIRST) {
+            TV f[NC];
 #pragma unroll
             for (int t = 0; t < VN; ++t) {
                 int x, y, z;
@@ -457,9 +480,13 @@ __device__ __forceinline__ void outer_tile(const OuterArgs& a, long tile) {
                 }
                 T uu[NC], ff[NC];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) uu[c] = u[c][t];
-                if (NC == 1 && a.other) ff[0] = react_coupled<T>(a.rxn, a.comp, uu[0], other[t]);
-                else react<T, NC>(a.rxn, uu, ff, x, y, z);
+                for (int c = 0; c < NC; ++c) uu[c] = g.v[i][c][t];
+                if constexpr (NC == 1) {
+                    if (a.other) ff[0] = react_coupled<T>(a.rxn, a.comp, uu[0], g.other[i][t]);
+                    else react<T, NC>(a.rxn, uu, ff, x, y, z);
+                } else {
+                    react<T, NC>(a.rxn, uu, ff, x, y, z);
+                }
 #pragma unroll
                 for (int c = 0; c < NC; ++c) f[c][t] = ff[c];
             }
@@ -467,23 +494,46 @@ __device__ __forceinline__ void outer_tile(const OuterArgs& a, long tile) {
             for (int c = 0; c < NC; ++c)
 #pragma unroll
                 for (int t = 0; t < VN; ++t) {
-                    X[c * AST + (j0 + t) * RS + k] = u[c][t];
+                    X[c * AST + (j0 + t) * RS + k] = g.v[i][c][t];
                     X[(NC + c) * AST + (j0 + t) * RS + k] = f[c][t];
                 }
         } else {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const TV g0 = *reinterpret_cast<const TV*>(in0 + gi + c * a.sc);
-                const TV g1 = *reinterpret_cast<const TV*>(in1 + gi + c * a.sc);
+            for (int c = 0; c < NC; ++c)
 #pragma unroll
                 for (int t = 0; t < VN; ++t) {
-                    X[c * AST + (j0 + t) * RS + k] = g0[t];
-                    X[(NC + c) * AST + (j0 + t) * RS + k] = g1[t];
+                    X[c * AST + (j0 + t) * RS + k] = g.v[i][c][t];
+                    X[(NC + c) * AST + (j0 + t) * RS + k] = g.v[i][NC + c][t];
                 }
-            }
         }
     }
-    __syncthreads();
+}
+
+// Workgroup: NP/(16 RB) waves over one tile of 16*CB columns; wave w owns
+// output row blocks RB*w .. RB*w+RB-1 for all CB column blocks (each P
+// fragment feeds 2*NC*CB MFMAs).  Runs on a staged tile: the inputs (and f
+// of them) in LDS, then the scaled spectral coefficients.
+template <typename M, int NC, bool FIRST, int RB, int CB>
+__device__ __forceinline__ void outer_compute(const OuterArgs& a, long tile) {
+    typedef typename M::elem T;
+    typedef typename Vec4<T>::type T4;
+    constexpr int NCOL = 16 * CB;         // columns per tile
+    constexpr int NA = 2 * NC;
+    constexpr int NQ = NA * CB;           // B fragments per K block
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* X = reinterpret_cast<T*>(smem_raw);
+
+    const int NP = a.NP;
+    const int RS = NP + 16 / int(sizeof(T));     // LDS stride between columns
+    const int AST = NCOL * RS;
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int li = lane & 15, lg = lane >> 4;
+    const int cb = int(tile % a.ncb);
+    const long bt = tile / a.ncb;
+    const long gbase = bt * a.sb + long(cb) * NCOL;
+    const void* __restrict__ P = a.P;
 
     const int rb0 = RB * w;
     // fragment qq = array (qq / CB), column block (qq % CB)
@@ -540,6 +590,16 @@ __device__ __forceinline__ void outer_tile(const OuterArgs& a, long tile) {
         }
 }
 
+// One tile, staged and computed.
+template <typename M, int NC, bool FIRST, int RB, int CB>
+__device__ __forceinline__ void outer_tile(const OuterArgs& a, long tile) {
+    OuterRegs<M, NC, FIRST, RB, CB> g;
+    outer_load<M, NC, FIRST, RB, CB>(a, tile, g);
+    outer_store<M, NC, FIRST, RB, CB>(a, tile, g);
+    __syncthreads();
+    outer_compute<M, NC, FIRST, RB, CB>(a, tile);
+}
+
 template <typename M, int NC, bool FIRST, int RB, int CB, int MAXT>
 __global__ __launch_bounds__(MAXT) void outer_stage(OuterArgs a) {
     outer_tile<M, NC, FIRST, RB, CB>(a, blockIdx.x);
@@ -569,44 +629,86 @@ struct XArgs {
 // the spectral/physical x rows of blocks RB*w .. RB*w+RB-1 of every product,
 // for all CB line blocks.  LDS: [2*NC][16*CB lines][NP + pad]; arrays 0..NC-1
 // hold w3, then c, then e; arrays NC..2NC-1 hold w4, then d.
+// One thread's share of an x tile's inputs (w3 and w4 of every component):
+// ITER 16-byte vectors of each (the workgroup has exactly 4 NP / RB threads).
 template <typename M, int NC, int RB, int CB>
-__device__ __forceinline__ void x_tile(const XArgs& a, long tile) {
+struct XRegs {
+    static constexpr int ITER = 4 * RB * CB / Vec16<typename M::elem>::n;
+    typename Vec16<typename M::elem>::type v[ITER][2 * NC];
+};
+
+// The tile's lines are one contiguous run of 16*CB*NP elements per array.
+template <typename M, int NC, int RB, int CB>
+__device__ __forceinline__ void x_load(const XArgs& a, long tile, XRegs<M, NC, RB, CB>& g) {
     typedef typename M::elem T;
-    typedef typename Vec4<T>::type T4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
+    const int nvec = 16 * CB * a.NP / VN;
+    const long base = tile * 16 * CB * long(a.NP);
+    const T* __restrict__ w3 = static_cast<const T*>(a.w3);
+    const T* __restrict__ w4 = static_cast<const T*>(a.w4);
+#pragma unroll
+    for (int i = 0; i < XRegs<M, NC, RB, CB>::ITER; ++i) {
+        const int v = threadIdx.x + i * blockDim.x;
+        if (v >= nvec) break;
+        const long gi = base + long(v) * VN;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            g.v[i][c] = *reinterpret_cast<const TV*>(w3 + c * a.sc + gi);
+            g.v[i][NC + c] = *reinterpret_cast<const TV*>(w4 + c * a.sc + gi);
+        }
+    }
+}
+
+// LDS: [2*NC][16*CB lines][NP + pad]; arrays 0..NC-1 hold w3, NC..2NC-1 w4.
+template <typename M, int NC, int RB, int CB>
+__device__ __forceinline__ void x_store(const XArgs& a, const XRegs<M, NC, RB, CB>& g) {
+    typedef typename M::elem T;
+    typedef typename Vec16<T>::type TV;
+    constexpr int VN = Vec16<T>::n;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* R = reinterpret_cast<T*>(smem_raw);
+    const int NP = a.NP;
+    const int RS = NP + 16 / int(sizeof(T));
+    const int AST = 16 * CB * RS;
+    const int nvec = 16 * CB * NP / VN;
+    const int vpl = NP / VN;
+#pragma unroll
+    for (int i = 0; i < XRegs<M, NC, RB, CB>::ITER; ++i) {
+        const int v = threadIdx.x + i * blockDim.x;
+        if (v >= nvec) break;
+        const int j = v / vpl, x = (v - j * vpl) * VN;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            *reinterpret_cast<TV*>(R + c * AST + j * RS + x) = g.v[i][c];
+            *reinterpret_cast<TV*>(R + (NC + c) * AST + j * RS + x) = g.v[i][NC + c];
+        }
+    }
+}
+
+// Workgroup: NP/(16 RB) waves over 16*CB consecutive x-lines.  Wave w owns
+// the spectral/physical x rows of blocks RB*w .. RB*w+RB-1 of every product,
+// for all CB line blocks.  Runs on a staged tile; arrays 0..NC-1 then hold
+// c, then e, and arrays NC..2NC-1 hold d.
+template <typename M, int NC, int RB, int CB>
+__device__ __forceinline__ void x_compute(const XArgs& a, long tile) {
+    typedef typename M::elem T;
+    typedef typename Vec4<T>::type T4;
     constexpr int NA = 2 * NC;
     constexpr int NL = 16 * CB;           // lines per tile
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* R = reinterpret_cast<T*>(smem_raw);
 
     const int NP = a.NP;
-    const int RS = NP + kInnerRowPad;
+    const int RS = NP + 16 / int(sizeof(T));
     const int AST = NL * RS;
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
     const long line0 = tile * NL;
-    const T* __restrict__ w3 = static_cast<const T*>(a.w3);
-    const T* __restrict__ w4 = static_cast<const T*>(a.w4);
     const void* __restrict__ P = a.P;
     const T tau = T(a.tau);
-
-    // the tile's lines are one contiguous run of NL*NP elements
-    const int nvec = NL * NP / VN;
-    const int vpl = NP / VN;
-#pragma unroll 4
-    for (int v = tid; v < nvec; v += blockDim.x) {
-        const int j = v / vpl, x = (v - j * vpl) * VN;
-        const long gi = line0 * NP + long(v) * VN;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            *reinterpret_cast<TV*>(R + c * AST + j * RS + x) = *reinterpret_cast<const TV*>(w3 + c * a.sc + gi);
-            *reinterpret_cast<TV*>(R + (NC + c) * AST + j * RS + x) = *reinterpret_cast<const TV*>(w4 + c * a.sc + gi);
-        }
-    }
-    __syncthreads();
 
     const int rb0 = RB * w;
     // B fragment qq of arrays q0..: array q0 + qq/CB, line li + 16 (qq%CB), x = k0 .. k0+KL
@@ -721,6 +823,15 @@ __device__ __forceinline__ void x_tile(const XArgs& a, long tile) {
     }
 }
 
+template <typename M, int NC, int RB, int CB>
+__device__ __forceinline__ void x_tile(const XArgs& a, long tile) {
+    XRegs<M, NC, RB, CB> g;
+    x_load<M, NC, RB, CB>(a, tile, g);
+    x_store<M, NC, RB, CB>(a, g);
+    __syncthreads();
+    x_compute<M, NC, RB, CB>(a, tile);
+}
+
 template <typename M, int NC, int RB, int CB, int MAXT>
 __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
     x_tile<M, NC, RB, CB>(a, blockIdx.x);
@@ -813,7 +924,7 @@ __global__ __launch_bounds__(MAXT) void x_stage_w(XSplitArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* R = reinterpret_cast<T*>(smem_raw);
     const int NP = a.NP;
-    const int RS = NP + kInnerRowPad;
+    const int RS = NP + 16 / int(sizeof(T));
     const int AST = 16 * RS;
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -883,7 +994,7 @@ __global__ __launch_bounds__(MAXT) void x_stage_u(XSplitArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* R = reinterpret_cast<T*>(smem_raw);
     const int NP = a.NP;
-    const int RS = NP + kInnerRowPad;
+    const int RS = NP + 16 / int(sizeof(T));
     const int AST = 16 * RS;
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1018,7 +1129,7 @@ __global__ __launch_bounds__(MAXT) void x_adjoint(XAdjArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* R = reinterpret_cast<T*>(smem_raw);
     const int NP = a.NP;
-    const int RS = NP + kInnerRowPad;
+    const int RS = NP + 16 / int(sizeof(T));
     const int AST = 16 * RS;
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1196,7 +1307,7 @@ __global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* X = reinterpret_cast<T*>(smem_raw);
     const int NP = a.NP;
-    const int RS = NP + kInnerRowPad;
+    const int RS = NP + 16 / int(sizeof(T));
     const int AST = 16 * RS;
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1608,19 +1719,32 @@ int tile_threads(int NP) { return shape_threads(NP, rows_per_wave(NP)); }
     ((NP) <= 256 ? KERNEL(2, 512, __VA_ARGS__)                            \
                  : ((NP) <= 512 ? KERNEL(2, 1024, __VA_ARGS__) : KERNEL(4, 1024, __VA_ARGS__)))
 
-// Resident workgroups of a grouped kernel on the whole device (persistent
-// grid size), at most `ntiles`.
+// Workgroups of a kernel resident on the whole device at once (the grid of a
+// persistent launch).  Each launcher caches it per instantiation and LDS size.
 template <typename K>
-long persistent_grid(K kernel, int threads, size_t lds, long ntiles) {
+long resident_groups(K kernel, int threads, size_t lds) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), threads, lds) !=
             hipSuccess ||
         per_cu < 1 || cus < 1)
-        return ntiles;
-    return std::max(1L, std::min(ntiles, long(per_cu) * cus));
+        return 0;
+    return long(per_cu) * cus;
 }
+
+struct GridCache {
+    size_t lds = 0;
+    long resident = 0;
+    template <typename K>
+    long grid(K kernel, int threads, size_t l, long ntiles) {
+        if (l != lds || resident == 0) {
+            resident = resident_groups(kernel, threads, l);
+            lds = l;
+        }
+        return resident > 0 ? std::max(1L, std::min(ntiles, resident)) : ntiles;
+    }
+};
 
 template <typename M, int NC, bool FIRST, int RB, int CB, int MAXT>
 etd_status launch_outer_k(const OuterArgs& a, long ntiles, hipStream_t s) {
@@ -1642,9 +1766,10 @@ etd_status launch_outer_group_k(const Group<OuterArgs>& g, int NP, hipStream_t s
     const size_t lds = outer_lds_bytes(NP, 2 * NC, CB, sizeof(T));
     auto k = outer_group<M, NC, FIRST, RB, CB, MAXT>;
     static size_t done = 0;
+    static GridCache gc;
     HIP_TRY(set_lds(k, lds, done), "grouped outer stage LDS attribute");
     const int thr = shape_threads(NP, RB);
-    hipLaunchKernelGGL(k, dim3(unsigned(persistent_grid(k, thr, lds, g.ntiles))), dim3(thr), lds, s, g);
+    hipLaunchKernelGGL(k, dim3(unsigned(gc.grid(k, thr, lds, g.ntiles))), dim3(thr), lds, s, g);
     HIP_TRY(hipGetLastError(), "grouped outer stage launch");
     return ETD_OK;
 }
@@ -1718,9 +1843,10 @@ etd_status launch_x_group_k(const Group<XArgs>& g, int NP, hipStream_t s) {
     const size_t lds = x_lds_bytes(NP, 2 * NC, CB, sizeof(T));
     auto k = x_group<M, NC, RB, CB, MAXT>;
     static size_t done = 0;
+    static GridCache gc;
     HIP_TRY(set_lds(k, lds, done), "grouped x stage LDS attribute");
     const int thr = shape_threads(NP, RB);
-    hipLaunchKernelGGL(k, dim3(unsigned(persistent_grid(k, thr, lds, g.ntiles))), dim3(thr), lds, s, g);
+    hipLaunchKernelGGL(k, dim3(unsigned(gc.grid(k, thr, lds, g.ntiles))), dim3(thr), lds, s, g);
     HIP_TRY(hipGetLastError(), "grouped x stage launch");
     return ETD_OK;
 }
@@ -3038,6 +3164,7 @@ etd_status etd_plan_table(const etd_plan* plan, int which, int d, int comp, doub
     if (which == 0) src = &pl.lam[d][comp];
     else if (which == 1) src = &pl.P[d];
     else if (which >= 2 && which <= 4) src = &pl.rat[d][comp][which - 2];
+    else if (which >= 5 && which <= 7) src = &pl.inc[d][comp][which - 5];
     else return fail(ETD_EINVAL, "unknown table");
     if (count < src->size()) return fail(ETD_EINVAL, "output buffer too small");
     std::memcpy(out, src->data(), src->size() * sizeof(double));

@@ -16,8 +16,9 @@
 // Hadamard factors (Remark 1): 2 Re(r_l/(z - s)) equals the real rational
 // function, evaluated here directly.  The stepper uses the increment form
 // Q(z) = Q(0) + (Q(z) - Q(0)), so the factors are stored as Q1 - 1,
-// tau (Q2 - 1) and Q3 - 1/2, each written with a factor z taken out so that
-// no cancellation occurs as tau*lambda -> 0.
+// tau (Q2 - 1) and Q3 - 1/2, each written with a factor z taken out (rational
+// families) or from expm1 and Taylor series (exact exponentials) so that no
+// cancellation occurs as tau*lambda -> 0.
 #include "plan.hpp"
 
 #include <cmath>
@@ -32,9 +33,66 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// Exact-exponential family (the fully discrete scheme of Sec. 2.2 before any
+// Pade approximation): Q_1 = e^{-z}, Q_2 = phi_1(z) = (1 - e^{-z})/z,
+// Q_3 = phi_2(z) = (z - 1 + e^{-z})/z^2.  The closed forms of phi_1 - 1 and
+// phi_2 - 1/2 cancel as z -> 0, so below z = 2 they are summed from their
+// Taylor series sum_{k>=1} (-z)^k/(k+1)! and sum_{k>=1} (-z)^k/(k+2)!
+// (alternating, terms decreasing; 28 terms reach 1e-24 at z = 2), and e^{-z} - 1
+// comes from expm1.  Derivatives likewise.
+constexpr int kSeriesTerms = 28;
+
+void exact_family(double z, double out[3], double inc[3]) {
+    const double em1 = std::expm1(-z);    // e^{-z} - 1
+    inc[0] = em1;
+    if (z < 2.0) {
+        double t = 1.0, f1 = 1.0, f2 = 2.0, s1 = 0.0, s2 = 0.0;   // t = (-z)^k, f1 = (k+1)!, f2 = (k+2)!
+        for (int k = 1; k <= kSeriesTerms; ++k) {
+            t *= -z;
+            f1 *= double(k + 1);
+            f2 *= double(k + 2);
+            s1 += t / f1;
+            s2 += t / f2;
+        }
+        inc[1] = s1;
+        inc[2] = s2;
+    } else {
+        inc[1] = (-em1 - z) / z;
+        inc[2] = (z + em1) / (z * z) - 0.5;
+    }
+    out[0] = 1.0 + em1;
+    out[1] = 1.0 + inc[1];
+    out[2] = 0.5 + inc[2];
+}
+
+void exact_family_derivative(double z, double dq[3]) {
+    const double em1 = std::expm1(-z);
+    dq[0] = -(1.0 + em1);
+    if (z < 2.0) {
+        // d/dz sum (-z)^k/(k+m)! = sum_{k>=1} -k (-z)^(k-1)/(k+m)!
+        double t = 1.0, f1 = 1.0, f2 = 2.0, s1 = 0.0, s2 = 0.0;   // t = (-z)^(k-1)
+        for (int k = 1; k <= kSeriesTerms; ++k) {
+            f1 *= double(k + 1);
+            f2 *= double(k + 2);
+            s1 -= double(k) * t / f1;
+            s2 -= double(k) * t / f2;
+            t *= -z;
+        }
+        dq[1] = s1;
+        dq[2] = s2;
+    } else {
+        dq[1] = (z * (1.0 + em1) + em1) / (z * z);
+        dq[2] = -em1 / (z * z) - 2.0 * (z + em1) / (z * z * z);
+    }
+}
+
 // Derivatives Q_l'(z) of the rational factors (quotient rule on the
 // polynomial forms below).
 void rational_derivative(int pade, double z, double dq[3]) {
+    if (pade == 0) {
+        exact_family_derivative(z, dq);
+        return;
+    }
     if (pade == 4) {
         const double den = (((z + 4.0) * z + 12.0) * z + 24.0) * z + 24.0;
         const double dden = ((4.0 * z + 12.0) * z + 24.0) * z + 24.0;
@@ -52,9 +110,14 @@ void rational_derivative(int pade, double z, double dq[3]) {
     }
 }
 
-// Rational factors at z = tau*lambda >= 0.  out[0..2] = Q_1..Q_3 and
-// inc[0..2] = Q_1 - 1, Q_2 - 1, Q_3 - 1/2.
+// Factors at z = tau*lambda >= 0 (rational families, or the exact
+// exponentials for pade = 0).  out[0..2] = Q_1..Q_3 and inc[0..2] = Q_1 - 1,
+// Q_2 - 1, Q_3 - 1/2.
 void rational(int pade, double z, double out[3], double inc[3]) {
+    if (pade == 0) {
+        exact_family(z, out, inc);
+        return;
+    }
     if (pade == 4) {
         // P_{0,4} family (Sec. 5): R_1 = 24/den, R_2 = (z^3+4z^2+12z+24)/den,
         // R_3 = (z^3+3z^2+8z+12)/den, den = z^4+4z^3+12z^2+24z+24.
@@ -114,7 +177,7 @@ etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
     const bool two = p.rxn == ETD_RXN_FHN_CUBIC || p.rxn == ETD_RXN_FHN_CLASSIC;
     if (p.rxn < ETD_RXN_NONE || p.rxn > ETD_RXN_FHN_CLASSIC) return bad("unknown reaction");
     if (two != (p.ncomp == 2)) return bad("ncomp must be 2 exactly for the FitzHugh-Nagumo reactions");
-    if (p.pade != 2 && p.pade != 4) return bad("pade must be 2 or 4");
+    if (p.pade != 0 && p.pade != 2 && p.pade != 4) return bad("pade must be 0 (exact exponentials), 2 or 4");
     if (p.precision < ETD_FP64 || p.precision > ETD_BF16X6) return bad("unknown precision");
     if (!(p.tau > 0.0) || !std::isfinite(p.tau)) return bad("tau must be a finite positive number");
     if (!(p.q >= 0.0) || !std::isfinite(p.q)) return bad("q must be finite and >= 0");
@@ -170,14 +233,20 @@ etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
             }
         for (int c = 0; c < pl.nc; ++c) {
             pl.lam[d][c].resize(n);
-            for (int l = 0; l < 3; ++l) pl.rat[d][c][l].resize(n);
+            for (int l = 0; l < 3; ++l) {
+                pl.rat[d][c][l].resize(n);
+                pl.inc[d][c][l].resize(n);
+            }
             for (int j = 0; j < n; ++j) {
                 const double sn = std::sin((j + 1) * M_PI / (2.0 * (n + 1)));
                 const double lam = p.kappa[c] * 4.0 / (h * h) * sn * sn + p.q / p.dim;
                 pl.lam[d][c][j] = lam;
                 double q[3], inc[3];
                 rational(p.pade, p.tau * lam, q, inc);
-                for (int l = 0; l < 3; ++l) pl.rat[d][c][l][j] = q[l];
+                for (int l = 0; l < 3; ++l) {
+                    pl.rat[d][c][l][j] = q[l];
+                    pl.inc[d][c][l][j] = inc[l];
+                }
             }
         }
     }

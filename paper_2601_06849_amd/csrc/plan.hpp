@@ -20,17 +20,20 @@ constexpr int kMaxPadded = 1024;
 // LDS budget of one stage workgroup (bytes) and its largest wave count.
 constexpr size_t kMaxLds = 160 * 1024;
 constexpr int kMaxWaves = 16;
-// Row padding (elements) of the x-stage LDS tiles, against bank conflicts.
-constexpr int kInnerRowPad = 4;
+// Row padding of the LDS tiles: 16 bytes (2 FP64 or 4 FP32 elements), which
+// keeps rows 16-byte aligned and makes the row stride 4 banks modulo 64, so
+// neither the 16-byte B-fragment reads of 8 lanes nor the element accesses of
+// 16 lanes (one column each) share a bank.
+inline int row_pad(size_t elem) { return int(16 / elem); }
 
 // LDS footprint of an outer-stage tile (`arrays` fields of 16*cb columns,
 // each a run of NP contracted indices plus padding) and of an x-stage tile
 // (`arrays` fields of 16*cb lines x NP, plus padding).
 inline size_t outer_lds_bytes(int NP, int arrays, int cb, size_t elem) {
-    return size_t(arrays) * 16 * cb * (NP + kInnerRowPad) * elem;
+    return size_t(arrays) * 16 * cb * (NP + row_pad(elem)) * elem;
 }
 inline size_t x_lds_bytes(int NP, int arrays, int cb, size_t elem) {
-    return size_t(arrays) * 16 * cb * (NP + kInnerRowPad) * elem;
+    return size_t(arrays) * 16 * cb * (NP + row_pad(elem)) * elem;
 }
 // 16-row blocks per wave: a tile needs NP / (16 * rows_per_wave) waves.
 inline int rows_per_wave(int NP) { return NP <= 512 ? 2 : 4; }
@@ -84,6 +87,7 @@ struct Plan {
     std::vector<double> lam[3][2];          // eigenvalues of A_d (kappa_c applied)
     std::vector<double> P[3];               // n_d x n_d eigenvector matrix
     std::vector<double> rat[3][2][3];       // Q_l(tau lambda_j), l = 1..3
+    std::vector<double> inc[3][2][3];       // Q_1 - 1, Q_2 - 1, Q_3 - 1/2 at tau lambda_j
     Layout lay{};
     std::vector<uint8_t> image;             // host image of the table region
     size_t table_bytes = 0;                 // bytes of image (start of workspace)

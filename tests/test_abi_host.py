@@ -265,3 +265,64 @@ def test_batch_host_validation(etd):
     with pytest.raises(etd.EtdError) as ei:
         etd.etd_batch_create([fhn])
     assert ei.value.status == etd.ETD_EUNSUPPORTED
+
+
+def _phi_decimal(z, ell):
+    """Q_1 - 1, Q_2 - 1, Q_3 - 1/2 of the exact family at z, to 50 digits."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    Z = Decimal(float(z))   # the exact binary value
+    # e^{-z} by its Taylor series with argument halving
+    k = 0
+    while Z / (2 ** k) > 1:
+        k += 1
+    x = -Z / (2 ** k)
+    term, e = Decimal(1), Decimal(1)
+    for i in range(1, 80):
+        term *= x / i
+        e += term
+    for _ in range(k):
+        e *= e
+    if ell == 1:
+        return e - 1
+    if ell == 2:
+        return (1 - e) / Z - 1
+    return (Z - 1 + e) / (Z * Z) - Decimal("0.5")
+
+
+def test_exact_exponential_increments_to_full_precision(etd):
+    """The exact-exponential increments (expm1 and series) against 50-digit
+    decimal arithmetic, from tau*lambda = 1e-9 to 60, within a few ulps (a
+    cancelling closed form would lose up to all digits as tau*lambda -> 0)."""
+    for tau in (1e-10, 1e-6, 1e-3, 0.05, 2.0):
+        p = W.Problem(dim=2, n=(40, 3), kappa=(0.7,), q=0.3, tau=tau, reaction="fisher", pade=0)
+        plan = etd.etd_plan_create(p)
+        try:
+            lam = etd.etd_plan_table(plan, 0, 0, 0, 40)
+            for ell in (1, 2, 3):
+                got = etd.etd_plan_table(plan, 4 + ell, 0, 0, 40)
+                for j in range(0, 40, 3):
+                    ref = float(_phi_decimal(tau * lam[j], ell))
+                    assert abs(got[j] - ref) <= 1e-15 * abs(ref), (tau, j, ell, got[j], ref)
+        finally:
+            etd.etd_plan_destroy(plan)
+
+
+def test_exact_exponential_tables_match_block_expm(etd, oracle_mod):
+    """P diag(Q_l) P^T equals e^{-tau A}, phi_1(tau A), phi_2(tau A) formed by
+    the oracle from one block matrix exponential."""
+    from oracle import phi
+    p = W.Problem(dim=2, n=(30, 17), kappa=(0.4, 2.0), q=0.9, tau=0.03, reaction="fhn_cubic", pade=0,
+                  lo=(0.0, -1.0, 0.0), hi=(2.0, 1.5, 1.0))
+    plan = etd.etd_plan_create(p)
+    try:
+        for d in range(2):
+            n = p.n[d]
+            P = etd.etd_plan_table(plan, 1, d, 0, n * n).reshape(n, n)
+            for c in range(2):
+                ref = phi.phi_matrices(phi.stencil(p, d, c), p.tau)
+                for ell in (1, 2, 3):
+                    qv = etd.etd_plan_table(plan, 1 + ell, d, c, n)
+                    assert np.abs((P * qv) @ P.T - ref[ell - 1]).max() < 1e-13
+    finally:
+        etd.etd_plan_destroy(plan)

@@ -2072,6 +2072,43 @@ etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int ns
     return ETD_OK;
 }
 
+// One step from Uin to Uout (padded fields, any buffers) that keeps its stage
+// fields: f = [w1, w2, w3, w4, W] in 3-D, [w1, w2, W] in 2-D (w1, w2 the
+// first stage's outputs, W the x stage's).  Fused tiles only (the adjoint's
+// own limits imply them).
+template <typename M, int NC>
+etd_status replay_step(const Plan& pl, StageTimer& tm, char* ws, double tn, const void* Uin, void* Uout,
+                       char* const* f, hipStream_t s) {
+    typedef typename M::elem T;
+    const void* Pdir[3] = {ws + pl.lay.P[0], ws + pl.lay.P[1], ws + pl.lay.P[2]};
+    StepArgs a = step_args(pl, ws, Pdir);
+    a.outer[0].in0 = Uin;
+    a.outer[0].out0 = f[0];
+    a.outer[0].out1 = f[1];
+    if (pl.dim == 3) {
+        a.outer[1].in0 = f[0];
+        a.outer[1].in1 = f[1];
+        a.outer[1].out0 = f[2];
+        a.outer[1].out1 = f[3];
+        a.x.w3 = f[2];
+        a.x.w4 = f[3];
+        a.x.Wout = f[4];
+    } else {
+        a.x.w3 = f[0];
+        a.x.w4 = f[1];
+        a.x.Wout = f[2];
+    }
+    a.x.out = Uout;
+    for (int k = 0; k < a.nouter; ++k) {
+        a.outer[k].rxn = rxn_args(pl, ws, tn);
+        if (k == 0) TIMED(0, (launch_outer<M, NC, true>(a.outer[0], a.ocols[0], plan_tile(pl, a.odir[0]), s)));
+        else TIMED(1, (launch_outer<M, NC, false>(a.outer[1], a.ocols[1], plan_tile(pl, a.odir[1]), s)));
+    }
+    a.x.rxn = rxn_args(pl, ws, tn + pl.prob.tau);
+    TIMED(2, (launch_x<M, NC>(a.x, a.nlines, plan_tile(pl, 0), reinterpret_cast<T*>(ws + pl.lay.field[4]), s)));
+    return ETD_OK;
+}
+
 template <typename M>
 etd_status advance_m(const Plan& pl, StageTimer& tm, void* u, double t0, int nsteps, char* ws, hipStream_t s) {
     typedef typename M::elem T;
@@ -2094,7 +2131,11 @@ struct AdjLayout {
     int K = 1, nck = 1;          // segment length and number of checkpoints
     size_t field = 0;            // bytes per padded field
     size_t ck = 0, seg = 0;      // checkpoint and segment states
-    size_t Wf = 0, Ub = 0, A[4] = {0, 0, 0, 0};
+    // per step of a segment, the stage fields the reverse sweep reads:
+    // w1, w2, (3-D: w3, w4,) W, each `field` bytes, kSlotFields per step
+    int slot_fields = 0;
+    size_t slots = 0;
+    size_t Ub = 0, A[4] = {0, 0, 0, 0};
     // gradient slots of the x, y and z adjoint kernels and of the pointwise kernel
     size_t part[4] = {0, 0, 0, 0};
     long nslots[4] = {0, 0, 0, 0};
@@ -2126,8 +2167,9 @@ AdjLayout adjoint_layout(const Plan& pl, int nsteps) {
     off += size_t(L.nck) * L.field;
     L.seg = off;
     off += size_t(L.K) * L.field;
-    L.Wf = off;
-    off += L.field;
+    L.slot_fields = pl.dim == 3 ? 5 : 3;
+    L.slots = off;
+    off += size_t(L.K) * L.slot_fields * L.field;
     L.Ub = off;
     off += L.field;
     for (int i = 0; i < 4; ++i) {
@@ -2209,14 +2251,11 @@ etd_status adjoint_t(const Plan& pl, StageTimer& tm, const void* u0, double t0, 
     const int ng = NC + 1;
     auto F = [&](size_t off) { return reinterpret_cast<T*>(aws + off); };
     T* U = reinterpret_cast<T*>(ws + pl.lay.field[0]);
-    T* WA = reinterpret_cast<T*>(ws + pl.lay.field[1]);
-    T* WB = reinterpret_cast<T*>(ws + pl.lay.field[2]);
-    T* WC = reinterpret_cast<T*>(ws + pl.lay.field[3]);
-    T* WD = reinterpret_cast<T*>(ws + pl.lay.field[4]);
     T* ck = F(L.ck);
     T* seg = F(L.seg);
-    T* Wf = F(L.Wf);
     T* Ub = F(L.Ub);
+    // stage fields of step i of the segment
+    auto slot = [&](int i, int j) { return aws + L.slots + (size_t(i) * L.slot_fields + j) * L.field; };
     T* A[4] = {F(L.A[0]), F(L.A[1]), F(L.A[2]), F(L.A[3])};
     const size_t fe = L.field / sizeof(T);   // elements between consecutive fields
     const T* diag = reinterpret_cast<const T*>(ws + pl.lay.diag);
@@ -2243,25 +2282,29 @@ etd_status adjoint_t(const Plan& pl, StageTimer& tm, const void* u0, double t0, 
 
     for (int c = L.nck - 1; c >= 0; --c) {
         const int n0 = c * L.K, n1 = std::min(N, n0 + L.K);
-        // replay the segment, keeping every state
-        TRY(copy_f<T>(ck + c * fe, U, nf, s));
+        // replay the segment, keeping every state and every step's stage fields
+        TRY(copy_f<T>(ck + c * fe, seg, nf, s));
         for (int i = 0; i < n1 - n0; ++i) {
-            TRY(copy_f<T>(U, seg + i * fe, nf, s));
-            if (i + 1 < n1 - n0) TRY((run_steps<M, NC>(pl, tm, ws, t0 + (n0 + i) * tau, 1, s)));
+            char* f[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+            for (int j = 0; j < L.slot_fields; ++j) f[j] = slot(i, j);
+            void* out = i + 1 < n1 - n0 ? static_cast<void*>(seg + (i + 1) * fe) : static_cast<void*>(U);
+            TRY((replay_step<M, NC>(pl, tm, ws, t0 + (n0 + i) * tau, seg + i * fe, out, f, s)));
         }
         for (int i = n1 - n0 - 1; i >= 0; --i) {
             const int n = n0 + i;
             const double tn = t0 + n * tau, tn1 = t0 + (n + 1) * tau;
             T* Un = seg + i * fe;
-            // regenerate the stage fields of step n (w1, v1 in WA, WB; w, v in WC, WD; W in Wf)
-            TRY(copy_f<T>(Un, U, nf, s));
-            TRY((run_steps<M, NC>(pl, tm, ws, tn, 1, s, Wf)));
+            T* w1 = reinterpret_cast<T*>(slot(i, 0));
+            T* w2 = reinterpret_cast<T*>(slot(i, 1));
+            T* w3 = pl.dim == 3 ? reinterpret_cast<T*>(slot(i, 2)) : w1;
+            T* w4 = pl.dim == 3 ? reinterpret_cast<T*>(slot(i, 3)) : w2;
+            T* Wf = reinterpret_cast<T*>(slot(i, L.slot_fields - 1));
             // x direction
             XAdjArgs xa{};
             xa.ubar = Ub;
             xa.W = Wf;
-            xa.w = pl.dim == 3 ? WC : WA;
-            xa.v = pl.dim == 3 ? WD : WB;
+            xa.w = w3;
+            xa.v = w4;
             xa.wbar = A[0];
             xa.vbar = A[1];
             xa.P = ws + pl.lay.P[0];
@@ -2285,7 +2328,7 @@ etd_status adjoint_t(const Plan& pl, StageTimer& tm, const void* u0, double t0, 
             oa.rxn = rxn_args(pl, ws, tn);
             const T *Lw, *Lv;
             if (pl.dim == 3) {
-                oa.a0 = A[0]; oa.a1 = A[1]; oa.f0 = WA; oa.f1 = WB; oa.out0 = A[2]; oa.out1 = A[3];
+                oa.a0 = A[0]; oa.a1 = A[1]; oa.f0 = w1; oa.f1 = w2; oa.out0 = A[2]; oa.out1 = A[3];
                 oa.P = ws + pl.lay.P[1];
                 oa.diag = diag + long(kDiagY) * dstride;
                 oa.NP = py; oa.ncb = px / 16; oa.sk = px; oa.sb = long(px) * py;

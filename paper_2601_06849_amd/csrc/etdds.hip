@@ -1651,16 +1651,19 @@ hipError_t set_lds(K kernel, size_t bytes, size_t& done) {
 // Tile shape of a stage launch.  Every wave owns `rb` 16-row blocks of each
 // product (a tile has NP/(16 rb) waves) and a tile spans `cb` 16-column
 // (outer stages) or 16-line (x stage) blocks, so that each P fragment read
-// from L2 feeds 2*NC*cb MFMAs.  Instantiated (rb, cb, launch bound):
-// (2,1,512), (2,1,1024), (4,1,1024), (2,2,512); with an FP32 state also
-// (4,1,512), and for single-component x stages (2,4,512).
+// from L2 feeds 2*NC*cb MFMAs and each B fragment rb of them.  Instantiated
+// (rb, cb, launch bound): (1,1,1024), (1,2,1024), (2,1,512), (2,1,1024),
+// (4,1,1024), (2,2,512); with an FP32 state also (4,1,512), and for
+// single-component x stages (2,4,512).
 //
-// The default shape, measured on the 255^3 workload: rb = 2 up to NP = 512
-// and 4 beyond; two column blocks in the outer stages only with an FP32 state
-// (in FP64 two workgroups per CU at one block beat the wider tile); x tiles
-// of four line blocks for single-component FP32-state systems, two for any
-// other FP32 state or single-component FP64 system (a two-component FP64
-// tile would spill).  An autotuned plan times every valid shape instead.
+// The default shape, measured on the 255^3 workload: for single-component
+// FP64 systems up to NP = 256, one row block per wave over two column or line
+// blocks (16 waves on one 132 KB tile: 2-5% faster than two row blocks per
+// wave); otherwise rb = 2 up to NP = 512 and 4 beyond, two column blocks in
+// the outer stages with an FP32 state, and x tiles of four line blocks for
+// single-component FP32-state systems, two for other FP32 states (a
+// two-component FP64 tile would spill).  An autotuned plan times every valid
+// shape instead.
 struct TileShape {
     int rb = 0, cb = 0;   // rb == 0: use the default
 };
@@ -1669,7 +1672,7 @@ int shape_threads(int NP, int rb) { return 64 * (NP / (16 * rb)); }
 
 template <typename T>
 bool shape_rows_ok(int NP, int rb) {
-    if (rb != 2 && rb != 4) return false;
+    if (rb != 1 && rb != 2 && rb != 4) return false;
     if (NP % (16 * rb) != 0 || NP / (16 * rb) > kMaxWaves) return false;
     return !(rb == 4 && shape_threads(NP, rb) <= 512 && sizeof(T) != 4);
 }
@@ -1678,7 +1681,7 @@ template <typename T, int NC>
 bool outer_shape_ok(int NP, TileShape t) {
     if (!shape_rows_ok<T>(NP, t.rb)) return false;
     if (t.cb == 2) {
-        if (t.rb != 2 || shape_threads(NP, t.rb) > 512) return false;
+        if (t.rb == 4 || (t.rb == 2 && shape_threads(NP, t.rb) > 512)) return false;
     } else if (t.cb != 1) {
         return false;
     }
@@ -1689,8 +1692,8 @@ template <typename T, int NC>
 bool x_shape_ok(int NP, long nlines, TileShape t) {
     if (!shape_rows_ok<T>(NP, t.rb)) return false;
     if (t.cb == 2 || t.cb == 4) {
-        if (t.rb != 2 || shape_threads(NP, t.rb) > 512) return false;
-        if (t.cb == 4 && !(sizeof(T) == 4 && NC == 1)) return false;
+        if (t.rb == 4 || (t.rb == 2 && shape_threads(NP, t.rb) > 512)) return false;
+        if (t.cb == 4 && !(t.rb == 2 && sizeof(T) == 4 && NC == 1)) return false;
     } else if (t.cb != 1) {
         return false;
     }
@@ -1700,12 +1703,14 @@ bool x_shape_ok(int NP, long nlines, TileShape t) {
 
 template <typename T, int NC>
 TileShape default_outer_shape(int NP) {
+    if (sizeof(T) == 8 && NC == 1 && outer_shape_ok<T, NC>(NP, TileShape{1, 2})) return TileShape{1, 2};
     if (sizeof(T) == 4 && outer_shape_ok<T, NC>(NP, TileShape{2, 2})) return TileShape{2, 2};
     return TileShape{rows_per_wave(NP), 1};
 }
 
 template <typename T, int NC>
 TileShape default_x_shape(int NP, long nlines) {
+    if (sizeof(T) == 8 && NC == 1 && x_shape_ok<T, NC>(NP, nlines, TileShape{1, 2})) return TileShape{1, 2};
     if (sizeof(T) == 4 && NC == 1 && x_shape_ok<T, NC>(NP, nlines, TileShape{2, 4})) return TileShape{2, 4};
     if ((sizeof(T) == 4 || NC == 1) && x_shape_ok<T, NC>(NP, nlines, TileShape{2, 2})) return TileShape{2, 2};
     return TileShape{rows_per_wave(NP), 1};
@@ -1779,6 +1784,11 @@ etd_status launch_outer_group_k(const Group<OuterArgs>& g, int NP, hipStream_t s
 template <typename T, int NC, typename L>
 etd_status outer_by_shape(int NP, TileShape t, L&& launch) {
     const bool small = shape_threads(NP, t.rb) <= 512;
+    if (t.rb == 1)
+        return t.cb == 2 ? launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{},
+                                  std::integral_constant<int, 1024>{})
+                         : launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{},
+                                  std::integral_constant<int, 1024>{});
     if (t.cb == 2) return launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{},
                                  std::integral_constant<int, 512>{});
     if (t.rb == 2)
@@ -1854,6 +1864,11 @@ etd_status launch_x_group_k(const Group<XArgs>& g, int NP, hipStream_t s) {
 template <typename T, int NC, typename L>
 etd_status x_by_shape(int NP, TileShape t, L&& launch) {
     const bool small = shape_threads(NP, t.rb) <= 512;
+    if (t.rb == 1)
+        return t.cb == 2 ? launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{},
+                                  std::integral_constant<int, 1024>{})
+                         : launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{},
+                                  std::integral_constant<int, 1024>{});
     if (t.cb == 4) {
         if constexpr (sizeof(T) == 4 && NC == 1)
             return launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{},
@@ -2402,7 +2417,7 @@ etd_status timer_mark(StageTimer& t, int kind, bool begin, hipStream_t s) {
 template <typename T, int NC>
 std::vector<TileShape> outer_candidates(int NP) {
     std::vector<TileShape> v;
-    for (int rb : {2, 4})
+    for (int rb : {1, 2, 4})
         for (int cb : {1, 2})
             if (outer_shape_ok<T, NC>(NP, TileShape{rb, cb})) v.push_back(TileShape{rb, cb});
     return v;
@@ -2411,7 +2426,7 @@ std::vector<TileShape> outer_candidates(int NP) {
 template <typename T, int NC>
 std::vector<TileShape> x_candidates(int NP, long nlines) {
     std::vector<TileShape> v;
-    for (int rb : {2, 4})
+    for (int rb : {1, 2, 4})
         for (int cb : {1, 2, 4})
             if (x_shape_ok<T, NC>(NP, nlines, TileShape{rb, cb})) v.push_back(TileShape{rb, cb});
     return v;

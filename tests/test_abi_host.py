@@ -225,7 +225,7 @@ def test_tile_shapes_host_validation(etd):
     p64 = p.replace(n=(255, 96, 64), precision="fp64")
     plan = etd.etd_plan_create(p64)
     try:
-        assert etd.etd_plan_tiles(plan) == [(2, 2), (2, 1), (2, 1)]
+        assert etd.etd_plan_tiles(plan) == [(1, 2), (1, 2), (1, 2)]
         with pytest.raises(etd.EtdError):   # rb = 4 at <= 8 waves is built for FP32 states only
             etd.etd_plan_set_tiles(plan, [(4, 1)])
     finally:

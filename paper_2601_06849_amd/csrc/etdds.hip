@@ -166,16 +166,25 @@ struct Bf16x6Mma {
         a.p[2] = *reinterpret_cast<const bf16x8*>(q + 2 * plane);
         return a;
     }
+    // Pairs of elements go through two-wide conversions, so that each packed
+    // round-to-nearest conversion serves two values and lands in place.
     __device__ static B prep(const vec_t<float, 8>& x) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        typedef __bf16 b2 __attribute__((ext_vector_type(2)));
         B b;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const __bf16 h = (__bf16)x[e];
-            const float r1 = x[e] - float(h);
-            const __bf16 m = (__bf16)r1;
-            b.p[0][e] = h;
-            b.p[1][e] = m;
-            b.p[2][e] = (__bf16)(r1 - float(m));
+        for (int e = 0; e < 8; e += 2) {
+            const f2 v = {x[e], x[e + 1]};
+            const b2 h = __builtin_convertvector(v, b2);
+            const f2 r1 = v - __builtin_convertvector(h, f2);
+            const b2 m = __builtin_convertvector(r1, b2);
+            const b2 l = __builtin_convertvector(r1 - __builtin_convertvector(m, f2), b2);
+            b.p[0][e] = h[0];
+            b.p[0][e + 1] = h[1];
+            b.p[1][e] = m[0];
+            b.p[1][e + 1] = m[1];
+            b.p[2][e] = l[0];
+            b.p[2][e + 1] = l[1];
         }
         return b;
     }
@@ -1693,7 +1702,7 @@ bool x_shape_ok(int NP, long nlines, TileShape t) {
     if (!shape_rows_ok<T>(NP, t.rb)) return false;
     if (t.cb == 2 || t.cb == 4) {
         if (t.rb == 4 || (t.rb == 2 && shape_threads(NP, t.rb) > 512)) return false;
-        if (t.cb == 4 && !(t.rb == 2 && sizeof(T) == 4 && NC == 1)) return false;
+        if (t.cb == 4 && !(sizeof(T) == 4 && NC == 1)) return false;
     } else if (t.cb != 1) {
         return false;
     }
@@ -1864,11 +1873,18 @@ etd_status launch_x_group_k(const Group<XArgs>& g, int NP, hipStream_t s) {
 template <typename T, int NC, typename L>
 etd_status x_by_shape(int NP, TileShape t, L&& launch) {
     const bool small = shape_threads(NP, t.rb) <= 512;
-    if (t.rb == 1)
+    if (t.rb == 1) {
+        if (t.cb == 4) {
+            if constexpr (sizeof(T) == 4 && NC == 1)
+                return launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 4>{},
+                              std::integral_constant<int, 1024>{});
+            return fail(ETD_EUNSUPPORTED, "tile shape not available for this system");
+        }
         return t.cb == 2 ? launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{},
                                   std::integral_constant<int, 1024>{})
                          : launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{},
                                   std::integral_constant<int, 1024>{});
+    }
     if (t.cb == 4) {
         if constexpr (sizeof(T) == 4 && NC == 1)
             return launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{},

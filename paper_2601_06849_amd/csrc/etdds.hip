@@ -847,6 +847,177 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Product-parallel path for 2-D problems.  A fused stage runs one workgroup
+// per 16 columns (or lines) over the whole contracted direction, so a 511^2
+// grid has only 32 tiles per stage.  Here every mode product is a launch of
+// its own over (row group) x (16-column tile) blocks, and the scalings, the
+// reaction and the increment-form residuals move into the epilogues; the
+// intermediates stay in L2/MALL (2 MB per field at 511^2).  Every output is
+// computed with the same operations in the same order as in the fused
+// stages.  The y stage takes two launches, the x stage four:
+//   YF: WC = dy .* (P U), WD = dy .* (P f(U))          (dy = Q1y - 1)
+//   YB: WA = U + P WC (= w3), WB = f(U) + P WD (= w4)
+//   X1: WC = d1 .* (P w3) + d2 .* (P w4)                (= c)
+//   X2: W = w3 + tau w4 + P c; WD = f(W) - w4 (= d); U = W + tau d / 2 (= V)
+//   X3: WC = d3 .* (P d)                                (= e)
+//   X4: U = V + tau P e
+// ---------------------------------------------------------------------------
+
+enum SplitKind { kSplitYF = 0, kSplitYB = 1, kSplitX1 = 2, kSplitX2 = 3, kSplitX3 = 4, kSplitX4 = 5 };
+
+struct SplitArgs {
+    void* U;              // padded fields, component stride sc
+    void* WA;
+    void* WB;
+    void* WC;
+    void* WD;
+    const void* P;        // NP x NP of the contracted direction
+    const void* diag;     // slot kDiagY (y kinds) or kDiagX1 (x kinds) of component 0
+    long diag_sstride, diag_cstride;
+    int NP;               // contracted (padded) extent
+    int npx;              // padded x extent (field row stride)
+    long sc;
+    double tau;
+    RxnArgs rxn;          // at t_n (y kinds) or t_{n+1} (x kinds)
+};
+
+// QP arrays are staged per pass (as many as the LDS holds), so each P
+// fragment feeds QP MFMAs per step.
+template <typename M, int NC, int KIND, int NW, int QP>
+__global__ __launch_bounds__(64 * NW) void split_product(SplitArgs a) {
+    typedef typename M::elem T;
+    typedef typename Vec4<T>::type T4;
+    constexpr bool YK = KIND <= kSplitYB;   // contracted direction y, columns are x
+    constexpr int NARR = (KIND <= kSplitX1) ? 2 * NC : NC;
+    static_assert(NARR % QP == 0, "passes must cover the arrays");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* X = reinterpret_cast<T*>(smem_raw);
+    const int NP = a.NP;
+    const int RS = NP + 16 / int(sizeof(T));
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int li = lane & 15, lg = lane >> 4;
+    const int rb0 = int(blockIdx.x) * NW + w;   // this wave's 16-row block
+    const int col0 = int(blockIdx.y) * 16;
+    const long sc = a.sc;
+    T* U = static_cast<T*>(a.U);
+    T* WA = static_cast<T*>(a.WA);
+    T* WB = static_cast<T*>(a.WB);
+    T* WC = static_cast<T*>(a.WC);
+    T* WD = static_cast<T*>(a.WD);
+    // element (contracted or output index k, column c of the tile)
+    auto at = [&](int k, int c) -> long {
+        return YK ? long(k) * a.npx + col0 + c : long(col0 + c) * a.npx + k;
+    };
+    auto coords = [&](int k, int c, int& x, int& y) {
+        x = YK ? col0 + c : k;
+        y = YK ? k : col0 + c;
+    };
+
+    const int AST = 16 * RS;
+    T4 acc[NARR / QP][1][QP];
+#pragma unroll
+    for (int q0 = 0; q0 < NARR; q0 += QP) {
+      // stage arrays q0 .. q0+QP-1 of the tile: X[array][column][k]
+#pragma unroll
+      for (int q = q0; q < q0 + QP; ++q) {
+        for (int v = tid; v < 16 * NP; v += blockDim.x) {
+            const int k = YK ? v / 16 : v % NP;
+            const int c = YK ? v % 16 : v / NP;
+            const long gi = at(k, c);
+            T val;
+            if constexpr (KIND == kSplitYF) {
+                if (q < NC) {
+                    val = U[gi + q * sc];
+                } else {
+                    T u[NC], f[NC];
+#pragma unroll
+                    for (int cc = 0; cc < NC; ++cc) u[cc] = U[gi + cc * sc];
+                    int x, y;
+                    coords(k, c, x, y);
+                    react<T, NC>(a.rxn, u, f, x, y, 0);
+                    val = f[q - NC];
+                }
+            } else if constexpr (KIND == kSplitYB) {
+                val = q < NC ? WC[gi + q * sc] : WD[gi + (q - NC) * sc];
+            } else if constexpr (KIND == kSplitX1) {
+                val = q < NC ? WA[gi + q * sc] : WB[gi + (q - NC) * sc];
+            } else if constexpr (KIND == kSplitX2 || KIND == kSplitX4) {
+                val = WC[gi + q * sc];
+            } else {
+                val = WD[gi + q * sc];
+            }
+            X[(q - q0) * AST + c * RS + k] = val;
+        }
+      }
+        __syncthreads();
+        zero<T, 1, QP>(acc[q0 / QP]);
+        gemm<M, 1, QP>(a.P, NP, rb0, li, lg, acc[q0 / QP],
+                       [&](int qq, int k0) { return lds_vec<T, M::KL>(X + qq * AST + li * RS + k0); });
+        __syncthreads();
+    }
+    // result of array q at register e
+    auto res = [&](int q, int e) { return acc[q / QP][0][q % QP][e]; };
+
+    const T* __restrict__ dg = static_cast<const T*>(a.diag);
+    const T tau = T(a.tau);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int k = 16 * rb0 + M::row(lg, e);
+        const long gi = at(k, li);
+        int x, y;
+        coords(k, li, x, y);
+        if constexpr (KIND == kSplitYF) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const T d = dg[c * a.diag_cstride + k];
+                WC[gi + c * sc] = res(c, e) * d;
+                WD[gi + c * sc] = res(NC + c, e) * d;
+            }
+        } else if constexpr (KIND == kSplitYB) {
+            T u[NC], f[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) u[c] = U[gi + c * sc];
+            react<T, NC>(a.rxn, u, f, x, y, 0);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                WA[gi + c * sc] = u[c] + res(c, e);
+                WB[gi + c * sc] = f[c] + res(NC + c, e);
+            }
+        } else if constexpr (KIND == kSplitX1) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const T* d1 = dg + c * a.diag_cstride;
+                const T* d2 = d1 + a.diag_sstride;
+                WC[gi + c * sc] = d1[k] * res(c, e) + d2[k] * res(NC + c, e);
+            }
+        } else if constexpr (KIND == kSplitX2) {
+            T Wv[NC], F[NC], w4[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                w4[c] = WB[gi + c * sc];
+                Wv[c] = WA[gi + c * sc] + tau * w4[c] + res(c, e);
+            }
+            react<T, NC>(a.rxn, Wv, F, x, y, 0);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const T d = F[c] - w4[c];
+                WD[gi + c * sc] = d;
+                U[gi + c * sc] = Wv[c] + T(0.5) * tau * d;
+            }
+        } else if constexpr (KIND == kSplitX3) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                WC[gi + c * sc] = dg[c * a.diag_cstride + 2 * a.diag_sstride + k] * res(c, e);
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) U[gi + c * sc] = U[gi + c * sc] + tau * res(c, e);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Grouped (batched) launches: one persistent launch runs a stage for every
 // instance of a shape class.  Instance i owns tiles start[i] .. start[i+1]-1
 // of the launch; workgroups stride over the tiles, find their instance by
@@ -2110,10 +2281,83 @@ StepArgs step_args(const Plan& pl, char* ws, const void* const Pdir[3]) {
     return a;
 }
 
+// One product-parallel launch: row groups of 16*NW rows x 16-column tiles.
+template <typename M, int NC, int KIND, int NW, int QP>
+etd_status launch_split_k(const SplitArgs& a, long ncols, hipStream_t s) {
+    typedef typename M::elem T;
+    const size_t lds = size_t(QP) * 16 * (a.NP + 16 / sizeof(T)) * sizeof(T);
+    auto k = split_product<M, NC, KIND, NW, QP>;
+    static size_t done = 0;
+    HIP_TRY(set_lds(k, lds, done), "2-D product LDS attribute");
+    hipLaunchKernelGGL(k, dim3(unsigned(a.NP / (16 * NW)), unsigned(ncols / 16)), dim3(64 * NW), lds, s, a);
+    HIP_TRY(hipGetLastError(), "2-D product launch");
+    return ETD_OK;
+}
+
+template <typename M, int NC, int KIND, int NW>
+etd_status launch_split_nw(const SplitArgs& a, long ncols, hipStream_t s) {
+    typedef typename M::elem T;
+    constexpr int NARR = (KIND <= kSplitX1) ? 2 * NC : NC;
+    const size_t per = size_t(16) * (a.NP + 16 / sizeof(T)) * sizeof(T);
+    if constexpr (NARR % 4 == 0)
+        if (4 * per <= kMaxLds) return launch_split_k<M, NC, KIND, NW, 4>(a, ncols, s);
+    if constexpr (NARR % 2 == 0)
+        if (2 * per <= kMaxLds) return launch_split_k<M, NC, KIND, NW, 2>(a, ncols, s);
+    return launch_split_k<M, NC, KIND, NW, 1>(a, ncols, s);
+}
+
+template <typename M, int NC, int KIND>
+etd_status launch_split(const SplitArgs& a, long ncols, hipStream_t s) {
+    return a.NP % 64 == 0 ? launch_split_nw<M, NC, KIND, 4>(a, ncols, s) : launch_split_nw<M, NC, KIND, 2>(a, ncols, s);
+}
+
+// 2-D problems take the product-parallel path when it has at least 128
+// blocks per launch (NP_y / 64 row groups x NP_x / 16 column tiles; from
+// about 512^2 on), where the fused stages would have only NP_x / 16 tiles.
+bool use_split2d(const Plan& pl) { return pl.dim == 2 && long(pl.np[1] / 64) * (pl.np[0] / 16) >= 128; }
+
+template <typename M, int NC>
+etd_status run_steps_split2d(const Plan& pl, StageTimer& tm, char* ws, double t0, int nsteps, hipStream_t s) {
+    typedef typename M::elem T;
+    const long dstride = long(pl.diag_stride);
+    const char* diag = ws + pl.lay.diag;
+    SplitArgs a{};
+    a.U = ws + pl.lay.field[0];
+    a.WA = ws + pl.lay.field[1];
+    a.WB = ws + pl.lay.field[2];
+    a.WC = ws + pl.lay.field[3];
+    a.WD = ws + pl.lay.field[4];
+    a.diag_sstride = dstride;
+    a.diag_cstride = long(kDiagSlots) * dstride;
+    a.npx = pl.np[0];
+    a.sc = long(pl.np[0]) * pl.np[1];
+    a.tau = pl.prob.tau;
+    SplitArgs y = a, x = a;
+    y.P = ws + pl.lay.P[1];
+    y.diag = diag + long(kDiagY) * dstride * pl.elem;
+    y.NP = pl.np[1];
+    x.P = ws + pl.lay.P[0];
+    x.diag = diag + long(kDiagX1) * dstride * pl.elem;
+    x.NP = pl.np[0];
+    const long nx = pl.np[0], ny = pl.np[1];
+    for (int step = 0; step < nsteps; ++step) {
+        y.rxn = rxn_args(pl, ws, t0 + step * pl.prob.tau);
+        x.rxn = rxn_args(pl, ws, t0 + (step + 1) * pl.prob.tau);
+        TIMED(0, (launch_split<M, NC, kSplitYF>(y, nx, s)));
+        TIMED(0, (launch_split<M, NC, kSplitYB>(y, nx, s)));
+        TIMED(2, (launch_split<M, NC, kSplitX1>(x, ny, s)));
+        TIMED(2, (launch_split<M, NC, kSplitX2>(x, ny, s)));
+        TIMED(2, (launch_split<M, NC, kSplitX3>(x, ny, s)));
+        TIMED(2, (launch_split<M, NC, kSplitX4>(x, ny, s)));
+    }
+    return ETD_OK;
+}
+
 template <typename M, int NC>
 etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int nsteps, hipStream_t s,
                      typename M::elem* w_out = nullptr) {
     typedef typename M::elem T;
+    if (w_out == nullptr && use_split2d(pl)) return run_steps_split2d<M, NC>(pl, tm, ws, t0, nsteps, s);
     const void* Pdir[3] = {ws + pl.lay.P[0], ws + pl.lay.P[1], ws + pl.lay.P[2]};
     StepArgs a = step_args(pl, ws, Pdir);
     a.x.Wout = w_out;

@@ -239,3 +239,24 @@ def test_batched_workload_sampled_against_oracle(etd, oracle_mod):
         print(f"  instance {i} n={p.n[0]} kappa={p.kappa[0]:.2e} q={p.q:.2f}: rel_l2 {err:.2e}")
         assert err <= FP32_TOL
     b.close()
+
+
+@pytest.mark.parametrize("precision,reaction", [("fp64", "fisher"), ("fp32", "fhn_cubic"), ("bf16x6", "fisher")])
+def test_product_parallel_2d_matches_fused_stages(etd, precision, reaction):
+    """Large 2-D single plans run every mode product as a launch of its own;
+    a batch of the same single problem runs the fused stage kernels.  Both
+    compute every output with the same operations in the same order."""
+    kw = dict(kappa=(1e-3, 1e-4)) if reaction == "fhn_cubic" else dict(kappa=(0.01,), q=0.3)
+    p = W.Problem(dim=2, n=(511, 480), tau=0.02, reaction=reaction, precision=precision, **kw)
+    u0 = W.u0_fhn_patch(p, 3, patch=0.3) if reaction == "fhn_cubic" else W.u0_sine_noise(p, 3)
+    st = etd.Stepper(p)
+    single = host(st.advance(st.field(u0), 6, 0.1))
+    st.close()
+    b = etd.Batch([p])
+    f = b.fields([u0])
+    b.advance(f, 6, t0=0.1)
+    fused = host(f[0])
+    b.close()
+    diff = np.abs(single - fused).max() / np.abs(fused).max()
+    print(f"  max rel diff {diff:.2e}")
+    assert diff <= (0.0 if precision == "fp64" else 1e-6) or np.array_equal(single, fused)

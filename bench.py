@@ -86,15 +86,16 @@ def timed_run(etd, torch, wl, precision, steps, warmup):
     return u, t1 - t0, ms, counts
 
 
-KERNEL_SOURCES = ("paper_2601_06849_amd/csrc/etdds.hip", "paper_2601_06849_amd/csrc/plan.hpp",
-                  "paper_2601_06849_amd/csrc/plan.cpp")
+CSRC = os.path.join(ROOT, "paper_2601_06849_amd", "csrc")
 
 
 def source_fingerprint():
+    """SHA-256 over every source of the library (csrc/, sorted by name)."""
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()
 
 

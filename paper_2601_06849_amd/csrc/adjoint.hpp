@@ -1,0 +1,285 @@
+// Host driver of the adjoint (sqrt(N) checkpointing).
+//
+// Part of libetdds: included, in order, by etdds.hip only (one translation
+// unit); every definition has internal linkage.
+#pragma once
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Adjoint driver: sqrt(N) checkpointing
+// ---------------------------------------------------------------------------
+
+struct AdjLayout {
+    int K = 1, nck = 1;          // segment length and number of checkpoints
+    size_t field = 0;            // bytes per padded field
+    size_t ck = 0, seg = 0;      // checkpoint and segment states
+    // per step of a segment, the stage fields the reverse sweep reads:
+    // w1, w2, (3-D: w3, w4,) W, each `field` bytes, kSlotFields per step
+    int slot_fields = 0;
+    size_t slots = 0;
+    size_t Ub = 0, A[4] = {0, 0, 0, 0};
+    // gradient slots of the x, y and z adjoint kernels and of the pointwise kernel
+    size_t part[4] = {0, 0, 0, 0};
+    long nslots[4] = {0, 0, 0, 0};
+    size_t gsum = 0;             // reduced gradient sums [4][NC + 1]
+    size_t total = 0;
+};
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr long kPointSlots = 2048;   // workgroups of the pointwise adjoint kernel
+
+AdjLayout adjoint_layout(const Plan& pl, int nsteps) {
+    AdjLayout L;
+    L.K = std::max(1, int(std::ceil(std::sqrt(double(std::max(nsteps, 1))))));
+    L.nck = (std::max(nsteps, 1) + L.K - 1) / L.K;
+    L.field = pl.lay.field_bytes;
+    const int ng = pl.nc + 1;
+    const int px = pl.np[0], py = pl.np[1], pz = pl.np[2];
+    L.nslots[0] = long(py) * pz / 16;
+    if (pl.dim == 3) {
+        L.nslots[1] = long(px) / 16 * pz;
+        L.nslots[2] = long(px) * py / 16;
+    } else {
+        L.nslots[1] = long(px) / 16;
+    }
+    L.nslots[3] = kPointSlots;
+    size_t off = 0;
+    L.ck = off;
+    off += size_t(L.nck) * L.field;
+    L.seg = off;
+    off += size_t(L.K) * L.field;
+    L.slot_fields = pl.dim == 3 ? 5 : 3;
+    L.slots = off;
+    off += size_t(L.K) * L.slot_fields * L.field;
+    L.Ub = off;
+    off += L.field;
+    for (int i = 0; i < 4; ++i) {
+        L.A[i] = off;
+        off += L.field;
+    }
+    for (int k = 0; k < 4; ++k) {
+        L.part[k] = off;
+        off = a256(off + size_t(std::max(L.nslots[k], 1L)) * ng * 8);
+    }
+    L.gsum = off;
+    off = a256(off + 4 * size_t(ng) * 8);
+    L.total = off;
+    return L;
+}
+
+size_t x_adjoint_lds(int NP, int nc, size_t elem) { return x_lds_bytes(NP, 8 * nc, 1, elem); }
+size_t outer_adjoint_lds(int NP, int nc, size_t elem) { return outer_lds_bytes(NP, 4 * nc, 1, elem); }
+constexpr size_t kStaticLds = 1024;   // the reduction scratch of add_partials
+
+etd_status adjoint_supported(const Plan& pl) {
+    const size_t e = pl.elem;
+    if (!x_fused(pl.np[0], pl.nc, e) || x_adjoint_lds(pl.np[0], pl.nc, e) + kStaticLds > kMaxLds)
+        return fail(ETD_EUNSUPPORTED, "the adjoint x tile exceeds the LDS budget at this size, precision and component count");
+    for (int d = 1; d < pl.dim; ++d)
+        if (outer_adjoint_lds(pl.np[d], pl.nc, e) + kStaticLds > kMaxLds)
+            return fail(ETD_EUNSUPPORTED, "the adjoint outer tile exceeds the LDS budget at this size and precision");
+    return ETD_OK;
+}
+
+template <typename M, int NC, int RB, int MAXT>
+etd_status launch_xadj_k(const XAdjArgs& a, long nlines, hipStream_t s) {
+    typedef typename M::elem T;
+    const size_t lds = x_adjoint_lds(a.NP, NC, sizeof(T));
+    auto k = x_adjoint<M, NC, RB, MAXT>;
+    static size_t done = 0;
+    HIP_TRY(set_lds(k, lds, done), "adjoint x LDS attribute");
+    hipLaunchKernelGGL(k, dim3(unsigned(nlines / 16)), dim3(shape_threads(a.NP, RB)), lds, s, a);
+    HIP_TRY(hipGetLastError(), "adjoint x launch");
+    return ETD_OK;
+}
+#define XADJ_K(RB, MAXT, M, NC, a, nl, s) launch_xadj_k<M, NC, RB, MAXT>(a, nl, s)
+
+// Adjoint tiles hold four (outer) or eight (x) fields per component, so at
+// small extents few workgroups fit per CU: one row block per wave up to
+// NP = 128 doubles their waves (the adjoint kernels of a 127^3 two-component
+// FP32 step: 0.335 -> 0.296 ms).
+#define ADJ_SHAPE(NP, KERNEL, ...) ((NP) <= 128 ? KERNEL(1, 512, __VA_ARGS__) : DISPATCH_SHAPE(NP, KERNEL, __VA_ARGS__))
+
+template <typename M, int NC, bool FIRST, int RB, int MAXT>
+etd_status launch_oadj_k(const OuterAdjArgs& a, long nblocks, hipStream_t s) {
+    typedef typename M::elem T;
+    const size_t lds = outer_adjoint_lds(a.NP, NC, sizeof(T));
+    auto k = outer_adjoint<M, NC, FIRST, RB, MAXT>;
+    static size_t done = 0;
+    HIP_TRY(set_lds(k, lds, done), "adjoint outer LDS attribute");
+    hipLaunchKernelGGL(k, dim3(unsigned(nblocks)), dim3(shape_threads(a.NP, RB)), lds, s, a);
+    HIP_TRY(hipGetLastError(), "adjoint outer launch");
+    return ETD_OK;
+}
+#define OADJ_K(RB, MAXT, M, NC, FIRST, a, nb, s) launch_oadj_k<M, NC, FIRST, RB, MAXT>(a, nb, s)
+
+template <typename T>
+etd_status copy_f(const T* src, T* dst, long n, hipStream_t s) {
+    hipLaunchKernelGGL(copy_field<T>, dim3(2048), dim3(256), 0, s, src, dst, n);
+    HIP_TRY(hipGetLastError(), "copy launch");
+    return ETD_OK;
+}
+
+#define TRY(expr)                          \
+    do {                                   \
+        const etd_status st_ = (expr);     \
+        if (st_ != ETD_OK) return st_;     \
+    } while (0)
+
+template <typename M, int NC>
+etd_status adjoint_t(const Plan& pl, StageTimer& tm, const void* u0, double t0, int N, const void* ubarN,
+                     void* ubar0, double* grad, char* ws, char* aws, const AdjLayout& L, hipStream_t s) {
+    typedef typename M::elem T;
+    const int px = pl.np[0], py = pl.np[1], pz = pl.np[2];
+    const long sc = long(px) * py * pz;
+    const long nf = sc * NC;   // elements per field
+    const double tau = pl.prob.tau;
+    const Dims dm = dims_of(pl);
+    const int ng = NC + 1;
+    auto F = [&](size_t off) { return reinterpret_cast<T*>(aws + off); };
+    T* U = reinterpret_cast<T*>(ws + pl.lay.field[0]);
+    T* ck = F(L.ck);
+    T* seg = F(L.seg);
+    T* Ub = F(L.Ub);
+    // stage fields of step i of the segment
+    auto slot = [&](int i, int j) { return aws + L.slots + (size_t(i) * L.slot_fields + j) * L.field; };
+    T* A[4] = {F(L.A[0]), F(L.A[1]), F(L.A[2]), F(L.A[3])};
+    const size_t fe = L.field / sizeof(T);   // elements between consecutive fields
+    const T* diag = reinterpret_cast<const T*>(ws + pl.lay.diag);
+    const long dstride = long(pl.diag_stride), dcs = long(kDiagSlots) * dstride;
+    const double* gtab = reinterpret_cast<const double*>(ws + pl.lay.grad);
+
+    // ---- forward pass: checkpoints every K steps ----
+    hipLaunchKernelGGL(pack_field<T>, dim3(2048), dim3(256), 0, s, static_cast<const T*>(u0), U, dm);
+    HIP_TRY(hipGetLastError(), "pack launch");
+    for (int c = 0; c < L.nck; ++c) {
+        TRY(copy_f<T>(U, ck + c * fe, nf, s));
+        const int n0 = c * L.K, n1 = std::min(N, n0 + L.K);
+        if (c + 1 < L.nck) TRY((run_steps<M, NC>(pl, tm, ws, t0 + n0 * tau, n1 - n0, s)));
+    }
+    // ---- adjoint state and gradient slots ----
+    hipLaunchKernelGGL(pack_field<T>, dim3(2048), dim3(256), 0, s, static_cast<const T*>(ubarN), Ub, dm);
+    HIP_TRY(hipGetLastError(), "pack launch");
+    for (int k = 0; k < 4; ++k) {
+        hipLaunchKernelGGL(fill_zero, dim3(64), dim3(256), 0, s, reinterpret_cast<double*>(aws + L.part[k]),
+                           std::max(L.nslots[k], 1L) * ng);
+        HIP_TRY(hipGetLastError(), "fill launch");
+    }
+    const double inv_dim = 1.0 / pl.dim;
+
+    for (int c = L.nck - 1; c >= 0; --c) {
+        const int n0 = c * L.K, n1 = std::min(N, n0 + L.K);
+        // replay the segment, keeping every state and every step's stage fields
+        TRY(copy_f<T>(ck + c * fe, seg, nf, s));
+        for (int i = 0; i < n1 - n0; ++i) {
+            char* f[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+            for (int j = 0; j < L.slot_fields; ++j) f[j] = slot(i, j);
+            void* out = i + 1 < n1 - n0 ? static_cast<void*>(seg + (i + 1) * fe) : static_cast<void*>(U);
+            TRY((replay_step<M, NC>(pl, tm, ws, t0 + (n0 + i) * tau, seg + i * fe, out, f, s)));
+        }
+        for (int i = n1 - n0 - 1; i >= 0; --i) {
+            const int n = n0 + i;
+            const double tn = t0 + n * tau, tn1 = t0 + (n + 1) * tau;
+            T* Un = seg + i * fe;
+            T* w1 = reinterpret_cast<T*>(slot(i, 0));
+            T* w2 = reinterpret_cast<T*>(slot(i, 1));
+            T* w3 = pl.dim == 3 ? reinterpret_cast<T*>(slot(i, 2)) : w1;
+            T* w4 = pl.dim == 3 ? reinterpret_cast<T*>(slot(i, 3)) : w2;
+            T* Wf = reinterpret_cast<T*>(slot(i, L.slot_fields - 1));
+            // x direction
+            XAdjArgs xa{};
+            xa.ubar = Ub;
+            xa.W = Wf;
+            xa.w = w3;
+            xa.v = w4;
+            xa.wbar = A[0];
+            xa.vbar = A[1];
+            xa.P = ws + pl.lay.P[0];
+            xa.diag = diag + long(kDiagX1) * dstride;
+            xa.diag_sstride = dstride;
+            xa.diag_cstride = dcs;
+            xa.NP = px;
+            xa.sc = sc;
+            xa.npy = py;
+            xa.tau = tau;
+            xa.rxn = rxn_args(pl, ws, tn1);
+            xa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[0]), 0, inv_dim};
+            TRY(ADJ_SHAPE(px, XADJ_K, M, NC, xa, long(py) * pz, s));
+            // outer directions
+            OuterAdjArgs oa{};
+            oa.diag_cstride = dcs;
+            oa.sc = sc;
+            oa.npx = px;
+            oa.npy = py;
+            oa.dim = pl.dim;
+            oa.rxn = rxn_args(pl, ws, tn);
+            const T *Lw, *Lv;
+            if (pl.dim == 3) {
+                oa.a0 = A[0]; oa.a1 = A[1]; oa.f0 = w1; oa.f1 = w2; oa.out0 = A[2]; oa.out1 = A[3];
+                oa.P = ws + pl.lay.P[1];
+                oa.diag = diag + long(kDiagY) * dstride;
+                oa.NP = py; oa.ncb = px / 16; oa.sk = px; oa.sb = long(px) * py;
+                oa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[1]), 1, inv_dim};
+                TRY(ADJ_SHAPE(py, OADJ_K, M, NC, false, oa, long(px / 16) * pz, s));
+                oa.a0 = A[2]; oa.a1 = A[3]; oa.f0 = Un; oa.f1 = nullptr; oa.out0 = A[0]; oa.out1 = A[1];
+                oa.P = ws + pl.lay.P[2];
+                oa.diag = diag + long(kDiagZ) * dstride;
+                oa.NP = pz; oa.ncb = px * py / 16; oa.sk = long(px) * py; oa.sb = 0;
+                oa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[2]), 2, inv_dim};
+                TRY(ADJ_SHAPE(pz, OADJ_K, M, NC, true, oa, long(px) * py / 16, s));
+                Lw = A[0];
+                Lv = A[1];
+            } else {
+                oa.a0 = A[0]; oa.a1 = A[1]; oa.f0 = Un; oa.f1 = nullptr; oa.out0 = A[2]; oa.out1 = A[3];
+                oa.P = ws + pl.lay.P[1];
+                oa.diag = diag + long(kDiagY) * dstride;
+                oa.NP = py; oa.ncb = px / 16; oa.sk = px; oa.sb = 0;
+                oa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[1]), 1, inv_dim};
+                TRY(ADJ_SHAPE(py, OADJ_K, M, NC, true, oa, long(px / 16), s));
+                Lw = A[2];
+                Lv = A[3];
+            }
+            hipLaunchKernelGGL((add_jt_field<T, NC>), dim3(unsigned(kPointSlots)), dim3(256), 0, s, Un, Lw, Lv, Ub,
+                               sc, rxn_args(pl, ws, tn), px, py, reinterpret_cast<double*>(aws + L.part[3]));
+            HIP_TRY(hipGetLastError(), "adjoint pointwise launch");
+        }
+    }
+    hipLaunchKernelGGL(unpack_field<T>, dim3(2048), dim3(256), 0, s, Ub, static_cast<T*>(ubar0), dm);
+    HIP_TRY(hipGetLastError(), "unpack launch");
+    double* gs = reinterpret_cast<double*>(aws + L.gsum);
+    for (int k = 0; k < 4; ++k) {
+        hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, s, reinterpret_cast<const double*>(aws + L.part[k]),
+                           std::max(L.nslots[k], 1L), ng, gs + k * ng);
+        HIP_TRY(hipGetLastError(), "gradient reduction launch");
+    }
+    double host[4 * 3];
+    HIP_TRY(hipMemcpyAsync(host, gs, 4 * ng * sizeof(double), hipMemcpyDeviceToHost, s), "gradient copy");
+    HIP_TRY(hipStreamSynchronize(s), "gradient sync");
+    for (int k = 0; k < ng; ++k) grad[k] = host[k] + host[ng + k] + host[2 * ng + k] + host[3 * ng + k];
+    return ETD_OK;
+}
+
+etd_status check_ws(const Plan& pl, const void* ws) {
+    if (!ws) return fail(ETD_EWORKSPACE, "workspace pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(ETD_EWORKSPACE, "workspace must be 256-byte aligned");
+    (void)pl;
+    return ETD_OK;
+}
+
+// Record an event for the start (begin = true) or end of a stage launch.
+etd_status timer_mark(StageTimer& t, int kind, bool begin, hipStream_t s) {
+    if (!t.on) return ETD_OK;
+    if (t.used == t.pool.size()) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e), "timing event create");
+        t.pool.push_back(e);
+    }
+    HIP_TRY(hipEventRecord(t.pool[t.used], s), "timing event record");
+    ++t.used;
+    if (begin) t.kind.push_back(kind);
+    return ETD_OK;
+}
+
+}  // namespace

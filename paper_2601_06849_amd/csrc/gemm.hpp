@@ -1,0 +1,82 @@
+// The K-loop of one mode-product tile on the matrix cores.
+//
+// Part of libetdds: included, in order, by etdds.hip only (one translation
+// unit); every definition has internal linkage.
+#pragma once
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Shared pieces of the stage kernels
+// ---------------------------------------------------------------------------
+
+// acc[r][q] += P[16(rb0+r) .. +16][:] . B_q over the whole contracted length
+// NP (a multiple of M::KB).  The A operand comes straight from the row-major P
+// in global memory (L2-resident; each lane reads its KL contiguous entries)
+// and is double-buffered in registers one K block ahead; bload(q, k0) returns
+// the KL values of B fragment q for contracted indices k0 .. k0+KL of this
+// lane's column.
+template <typename M, int RB, int NQ, typename BL>
+__device__ __forceinline__ void gemm(const void* __restrict__ P, int NP, int rb0, int li, int lg,
+                                     vec_t<typename M::elem, 4> (&acc)[RB][NQ], BL bload) {
+    const int nkb = NP / M::KB;
+    long off[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) off[r] = long(16 * (rb0 + r) + li) * NP + M::KL * lg;
+    typename M::A a_cur[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) a_cur[r] = M::load_a(P, NP, off[r]);
+    for (int kb = 0; kb < nkb; ++kb) {
+        const int kn = min(kb + 1, nkb - 1) * M::KB;
+        typename M::A a_nxt[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) a_nxt[r] = M::load_a(P, NP, off[r] + kn);
+        if constexpr (M::SPLIT_B) {
+            // split B fragments one at a time (each expands to three pieces)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const typename M::B b = M::prep(bload(q, kb * M::KB + M::KL * lg));
+#pragma unroll
+                for (int t = 0; t < M::NSUB; ++t)
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) M::step(acc[r][q], a_cur[r], b, t);
+            }
+        } else {
+            typename M::B b[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) b[q] = M::prep(bload(q, kb * M::KB + M::KL * lg));
+#pragma unroll
+            for (int t = 0; t < M::NSUB; ++t)
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) M::step(acc[r][q], a_cur[r], b[q], t);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) a_cur[r] = a_nxt[r];
+    }
+}
+
+template <typename T, int RB, int NQ>
+__device__ __forceinline__ void zero(typename Vec4<T>::type (&acc)[RB][NQ]) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[r][q] = typename Vec4<T>::type{0, 0, 0, 0};
+}
+
+// 16-byte vector of T
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+    typedef double __attribute__((ext_vector_type(2))) type;
+    static constexpr int n = 2;
+};
+template <>
+struct Vec16<float> {
+    typedef float __attribute__((ext_vector_type(4))) type;
+    static constexpr int n = 4;
+};
+
+}  // namespace

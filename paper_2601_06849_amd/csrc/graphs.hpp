@@ -1,0 +1,25 @@
+// HIP graph capture helpers.
+//
+// Part of libetdds: included, in order, by etdds.hip only (one translation
+// unit); every definition has internal linkage.
+#pragma once
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// HIP graphs: the launches of a call captured once and replayed.
+// ---------------------------------------------------------------------------
+
+etd_status end_capture(hipStream_t s, etd_status st, hipGraph_t& g) {
+    g = nullptr;
+    const hipError_t he = hipStreamEndCapture(s, &g);
+    if (st != ETD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        g = nullptr;
+        return st;
+    }
+    if (he != hipSuccess) return hip_fail(he, "graph capture");
+    return ETD_OK;
+}
+
+}  // namespace

@@ -371,3 +371,27 @@ def test_saturating_blowup_is_flagged(etd):
         st.compare(u, ref)
     assert ei.value.status == etd.ETD_ENONFINITE
     st.close()
+
+
+# ---------------------------------------------------------------------------
+# extreme extents: one interior point in a direction, and the largest padded
+# extent of each direction (1024 in FP32, 576 for an FP64 tile)
+# ---------------------------------------------------------------------------
+
+EDGE = [
+    ("fp64", (1, 40)), ("fp64", (40, 1)), ("fp64", (3, 1, 5)), ("fp64", (1, 1, 1)),
+    ("fp32", (1023, 17, 9)), ("fp32", (9, 1023, 17)), ("fp32", (17, 9, 1023)),
+    ("fp64", (576, 9, 7)), ("fp64", (7, 576, 9)), ("fp64", (9, 7, 576)),
+    ("bf16x6", (1023, 33)), ("bf16x6", (20, 1023)),
+]
+
+
+@pytest.mark.parametrize("precision,n", EDGE, ids=lambda v: str(v))
+def test_extreme_extents(etd, oracle_mod, precision, n):
+    p = W.Problem(dim=len(n), n=n, kappa=(0.05,), q=0.3, tau=0.01, reaction="fisher", precision=precision)
+    u0 = W.u0_sine_noise(p, 1)
+    ref = oracle_mod.advance(p.replace(precision="fp64"), u0, 3)
+    got = run_gpu(etd, p, u0, 3)
+    err = rel_l2(got, ref)
+    print(f"  rel_l2={err:.3e}")
+    assert err <= (FP64_TOL if precision == "fp64" else REDUCED_TOL)

@@ -86,6 +86,32 @@ def test_fisher3d_n255_full_size_steps(etd, oracle_mod):
     check(etd, oracle_mod, wl.problem, wl.u0(), 3)
 
 
+_FISHER3D_REF = {}
+
+
+def fisher3d_reference(oracle_mod):
+    """The FP64 oracle over the whole benchmark run (255^3, 200 steps; ~20 s on
+    16 host cores), computed once for the tests below."""
+    if "ref" not in _FISHER3D_REF:
+        wl = W.fisher3d()
+        _FISHER3D_REF["ref"] = oracle_mod.advance(wl.problem, wl.u0(), wl.nsteps)
+    return _FISHER3D_REF["ref"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x6"])
+def test_fisher3d_n255_whole_benchmark_run(etd, oracle_mod, precision):
+    """The benchmark's workload and launch configuration (default tiles), all
+    200 steps, against the FP64 oracle: 1e-12 in FP64, 1e-6 for the reduced
+    mode products (the bound the benchmark's reduced variants are held to)."""
+    wl = W.fisher3d(precision=precision)
+    ref = fisher3d_reference(oracle_mod)
+    got = run_gpu(etd, wl.problem, wl.u0(), wl.nsteps)
+    err = rel_l2(got, ref)
+    print(f"  {precision} rel_l2={err:.3e} max_abs={np.abs(got - ref).max():.3e}")
+    assert np.all(np.isfinite(got))
+    assert err <= (FP64_TOL if precision == "fp64" else REDUCED_TOL)
+
+
 _FHN2D_REF = {}
 
 

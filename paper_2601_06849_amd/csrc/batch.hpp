@@ -175,30 +175,42 @@ etd_status batch_advance_t(Batch& B, void* const* u, double t0, int nsteps, char
     typedef typename M::elem T;
     const bool fork = B.groups.size() > 1;
     if (fork) HIP_TRY(hipEventRecord(B.fork, s), "batch fork record");
+    etd_status st = ETD_OK;
     for (BatchGroup& G : B.groups) {
         hipStream_t gs = fork ? G.stream : s;
-        if (fork) HIP_TRY(hipStreamWaitEvent(gs, B.fork, 0), "batch fork wait");
-        for (int i : G.inst) {
-            const Plan& pl = B.plans[i];
-            hipLaunchKernelGGL(pack_field<T>, dim3(1024), dim3(256), 0, gs, static_cast<const T*>(u[i]),
-                               reinterpret_cast<T*>(ws + B.base[i] + pl.lay.field[0]), dims_of(pl));
-        }
-        HIP_TRY(hipGetLastError(), "batch pack launch");
-        for (int step = 0; step < nsteps; ++step) {
-            for (int stage = 0; stage < B.dim - 1; ++stage) TRY((group_stage<M, NC>(B, G, stage, ws, t0, step, gs)));
-            TRY((group_stage<M, NC>(B, G, 2, ws, t0, step + 1, gs)));
-        }
-        for (int i : G.inst) {
-            const Plan& pl = B.plans[i];
-            hipLaunchKernelGGL(unpack_field<T>, dim3(1024), dim3(256), 0, gs,
-                               reinterpret_cast<const T*>(ws + B.base[i] + pl.lay.field[0]), static_cast<T*>(u[i]),
-                               dims_of(pl));
-        }
-        HIP_TRY(hipGetLastError(), "batch unpack launch");
         if (fork) {
-            HIP_TRY(hipEventRecord(G.done, gs), "batch join record");
-            HIP_TRY(hipStreamWaitEvent(s, G.done, 0), "batch join wait");
+            const hipError_t e = hipStreamWaitEvent(gs, B.fork, 0);
+            if (e != hipSuccess) return hip_fail(e, "batch fork wait");
         }
+        // the group's work; on an error the group is still joined below
+        st = [&]() -> etd_status {
+            for (int i : G.inst) {
+                const Plan& pl = B.plans[i];
+                hipLaunchKernelGGL(pack_field<T>, dim3(1024), dim3(256), 0, gs, static_cast<const T*>(u[i]),
+                                   reinterpret_cast<T*>(ws + B.base[i] + pl.lay.field[0]), dims_of(pl));
+            }
+            HIP_TRY(hipGetLastError(), "batch pack launch");
+            for (int step = 0; step < nsteps; ++step) {
+                for (int stage = 0; stage < B.dim - 1; ++stage)
+                    TRY((group_stage<M, NC>(B, G, stage, ws, t0, step, gs)));
+                TRY((group_stage<M, NC>(B, G, 2, ws, t0, step + 1, gs)));
+            }
+            for (int i : G.inst) {
+                const Plan& pl = B.plans[i];
+                hipLaunchKernelGGL(unpack_field<T>, dim3(1024), dim3(256), 0, gs,
+                                   reinterpret_cast<const T*>(ws + B.base[i] + pl.lay.field[0]),
+                                   static_cast<T*>(u[i]), dims_of(pl));
+            }
+            HIP_TRY(hipGetLastError(), "batch unpack launch");
+            return ETD_OK;
+        }();
+        if (fork) {
+            // join every forked group back to the caller's stream, also after an error
+            const hipError_t e1 = hipEventRecord(G.done, gs);
+            const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s, G.done, 0) : e1;
+            if (st == ETD_OK && e2 != hipSuccess) st = hip_fail(e2, "batch join");
+        }
+        if (st != ETD_OK) return st;
     }
     return ETD_OK;
 }

@@ -260,6 +260,22 @@ etd_status etd_plan_set_tiles(etd_plan* plan, const int tiles[6]) {
     return ETD_OK;
 }
 
+// A batch offers no table query and uploads only the packed image, so the
+// FP64 host tables of its instances (an n_d x n_d matrix per direction) are
+// dropped once the image is built.
+static void release_host_tables(Plan& pl) {
+    for (int d = 0; d < 3; ++d) {
+        std::vector<double>().swap(pl.P[d]);
+        for (int c = 0; c < 2; ++c) {
+            std::vector<double>().swap(pl.lam[d][c]);
+            for (int l = 0; l < 3; ++l) {
+                std::vector<double>().swap(pl.rat[d][c][l]);
+                std::vector<double>().swap(pl.inc[d][c][l]);
+            }
+        }
+    }
+}
+
 etd_status etd_batch_create(const etd_problem* probs, int count, etd_batch** out) {
     if (!probs || !out) return fail(ETD_EINVAL, "NULL argument");
     *out = nullptr;
@@ -285,6 +301,7 @@ etd_status etd_batch_create(const etd_problem* probs, int count, etd_batch** out
             return fail(ETD_EINVAL, "instance " + std::to_string(i) +
                                         ": a batch takes one dimension, component count and precision");
         }
+        release_host_tables(B.plans[i]);
         bool fused = x_fused(pl.np[0], pl.nc, pl.elem);
         for (int d = 1; d < pl.dim; ++d) fused = fused && outer_fused(pl.np[d], pl.nc, pl.elem);
         if (!fused) {

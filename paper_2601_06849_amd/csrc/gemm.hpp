@@ -13,47 +13,57 @@ namespace {
 // acc[r][q] += P[16(rb0+r) .. +16][:] . B_q over the whole contracted length
 // NP (a multiple of M::KB).  The A operand comes straight from the row-major P
 // in global memory (L2-resident; each lane reads its KL contiguous entries)
-// and is double-buffered in registers one K block ahead; bload(q, k0) returns
-// the KL values of B fragment q for contracted indices k0 .. k0+KL of this
-// lane's column.
-template <typename M, int RB, int NQ, typename BL>
+// and is held in a ring of PF register buffers, so each K block's fragment is
+// requested PF blocks before its use (PF = 1: one block ahead; launches with
+// one wave per SIMD need a deeper ring to cover the L2 latency); bload(q, k0)
+// returns the KL values of B fragment q for contracted indices k0 .. k0+KL of
+// this lane's column.
+template <typename M, int RB, int NQ, int PF = 1, typename BL>
 __device__ __forceinline__ void gemm(const void* __restrict__ P, int NP, int rb0, int li, int lg,
                                      vec_t<typename M::elem, 4> (&acc)[RB][NQ], BL bload) {
     const int nkb = NP / M::KB;
     long off[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) off[r] = long(16 * (rb0 + r) + li) * NP + M::KL * lg;
-    typename M::A a_cur[RB];
+    // ring[i] holds K block kb + i (addresses clamp to the last block)
+    typename M::A ring[PF][RB];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) a_cur[r] = M::load_a(P, NP, off[r]);
-    for (int kb = 0; kb < nkb; ++kb) {
-        const int kn = min(kb + 1, nkb - 1) * M::KB;
-        typename M::A a_nxt[RB];
+    for (int i = 0; i < PF; ++i)
 #pragma unroll
-        for (int r = 0; r < RB; ++r) a_nxt[r] = M::load_a(P, NP, off[r] + kn);
-        if constexpr (M::SPLIT_B) {
-            // split B fragments one at a time (each expands to three pieces)
+        for (int r = 0; r < RB; ++r) ring[i][r] = M::load_a(P, NP, off[r] + min(i, nkb - 1) * M::KB);
+    for (int kb0 = 0; kb0 < nkb; kb0 += PF) {
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const typename M::B b = M::prep(bload(q, kb * M::KB + M::KL * lg));
+        for (int i = 0; i < PF; ++i) {
+            const int kb = kb0 + i;
+            if (PF > 1 && kb >= nkb) break;
+            typename M::A a_cur[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) a_cur[r] = ring[i][r];
+            const int kn = min(kb + PF, nkb - 1) * M::KB;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) ring[i][r] = M::load_a(P, NP, off[r] + kn);
+            if constexpr (M::SPLIT_B) {
+                // split B fragments one at a time (each expands to three pieces)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const typename M::B b = M::prep(bload(q, kb * M::KB + M::KL * lg));
+#pragma unroll
+                    for (int t = 0; t < M::NSUB; ++t)
+#pragma unroll
+                        for (int r = 0; r < RB; ++r) M::step(acc[r][q], a_cur[r], b, t);
+                }
+            } else {
+                typename M::B b[NQ];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) b[q] = M::prep(bload(q, kb * M::KB + M::KL * lg));
 #pragma unroll
                 for (int t = 0; t < M::NSUB; ++t)
 #pragma unroll
-                    for (int r = 0; r < RB; ++r) M::step(acc[r][q], a_cur[r], b, t);
+                    for (int r = 0; r < RB; ++r)
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) M::step(acc[r][q], a_cur[r], b[q], t);
             }
-        } else {
-            typename M::B b[NQ];
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) b[q] = M::prep(bload(q, kb * M::KB + M::KL * lg));
-#pragma unroll
-            for (int t = 0; t < M::NSUB; ++t)
-#pragma unroll
-                for (int r = 0; r < RB; ++r)
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q) M::step(acc[r][q], a_cur[r], b[q], t);
         }
-#pragma unroll
-        for (int r = 0; r < RB; ++r) a_cur[r] = a_nxt[r];
     }
 }
 

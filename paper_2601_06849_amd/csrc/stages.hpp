@@ -550,44 +550,94 @@ __global__ __launch_bounds__(64 * NW) void split_product(SplitArgs a) {
     };
 
     const int AST = 16 * RS;
+    // Staging moves 16-byte chunks of VN elements: VN consecutive columns of
+    // one contracted index k (y kinds, x contiguous) or VN consecutive k of
+    // one line (x kinds).  Every padded extent is a multiple of VN and every
+    // field is 256-byte aligned, so each chunk is one aligned vector load.
+    typedef typename Vec16<T>::type TV;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int UNR = 8;   // chunks per array in flight per thread
+    const int nchunk = 16 * NP / VN;
+    auto chunk = [&](int v, int& k, int& c) {
+        if constexpr (YK) {
+            k = v / (16 / VN);
+            c = (v % (16 / VN)) * VN;
+        } else {
+            c = v / (NP / VN);
+            k = (v % (NP / VN)) * VN;
+        }
+    };
+    auto vload = [&](const T* base, long gi) { return *reinterpret_cast<const TV*>(base + gi); };
+    // chunk of array q at (k, c)
+    auto fetch = [&](int q, int k, int c) -> TV {
+        const long gi = at(k, c);
+        if constexpr (KIND == kSplitYF) {
+            if (q < NC) return vload(U, gi + q * sc);
+            TV u[NC];
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) u[cc] = vload(U, gi + cc * sc);
+            TV r;
+#pragma unroll
+            for (int j = 0; j < VN; ++j) {
+                T uj[NC], f[NC];
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc) uj[cc] = u[cc][j];
+                int x, y;
+                coords(k, c + j, x, y);
+                react<T, NC>(a.rxn, uj, f, x, y, 0);
+                r[j] = f[q - NC];
+            }
+            return r;
+        } else if constexpr (KIND == kSplitYB) {
+            return q < NC ? vload(WC, gi + q * sc) : vload(WD, gi + (q - NC) * sc);
+        } else if constexpr (KIND == kSplitX1) {
+            return q < NC ? vload(WA, gi + q * sc) : vload(WB, gi + (q - NC) * sc);
+        } else if constexpr (KIND == kSplitX2 || KIND == kSplitX4) {
+            return vload(WC, gi + q * sc);
+        } else {
+            return vload(WD, gi + q * sc);
+        }
+    };
     T4 acc[NARR / QP][1][QP];
 #pragma unroll
     for (int q0 = 0; q0 < NARR; q0 += QP) {
-      // stage arrays q0 .. q0+QP-1 of the tile: X[array][column][k]
+        // stage arrays q0 .. q0+QP-1 of the tile: X[array][column][k]; all
+        // loads of a round are issued before its LDS stores
+        for (int v0 = tid; v0 < nchunk; v0 += UNR * int(blockDim.x)) {
+            TV val[QP][UNR];
 #pragma unroll
-      for (int q = q0; q < q0 + QP; ++q) {
-        for (int v = tid; v < 16 * NP; v += blockDim.x) {
-            const int k = YK ? v / 16 : v % NP;
-            const int c = YK ? v % 16 : v / NP;
-            const long gi = at(k, c);
-            T val;
-            if constexpr (KIND == kSplitYF) {
-                if (q < NC) {
-                    val = U[gi + q * sc];
-                } else {
-                    T u[NC], f[NC];
+            for (int j = 0; j < UNR; ++j) {
+                const int v = v0 + j * int(blockDim.x);
+                if (v < nchunk) {
+                    int k, c;
+                    chunk(v, k, c);
 #pragma unroll
-                    for (int cc = 0; cc < NC; ++cc) u[cc] = U[gi + cc * sc];
-                    int x, y;
-                    coords(k, c, x, y);
-                    react<T, NC>(a.rxn, u, f, x, y, 0);
-                    val = f[q - NC];
+                    for (int q = 0; q < QP; ++q) val[q][j] = fetch(q0 + q, k, c);
                 }
-            } else if constexpr (KIND == kSplitYB) {
-                val = q < NC ? WC[gi + q * sc] : WD[gi + (q - NC) * sc];
-            } else if constexpr (KIND == kSplitX1) {
-                val = q < NC ? WA[gi + q * sc] : WB[gi + (q - NC) * sc];
-            } else if constexpr (KIND == kSplitX2 || KIND == kSplitX4) {
-                val = WC[gi + q * sc];
-            } else {
-                val = WD[gi + q * sc];
             }
-            X[(q - q0) * AST + c * RS + k] = val;
+#pragma unroll
+            for (int j = 0; j < UNR; ++j) {
+                const int v = v0 + j * int(blockDim.x);
+                if (v < nchunk) {
+                    int k, c;
+                    chunk(v, k, c);
+#pragma unroll
+                    for (int q = 0; q < QP; ++q) {
+                        T* dst = X + q * AST + c * RS + k;
+                        if constexpr (YK) {
+#pragma unroll
+                            for (int e = 0; e < VN; ++e) dst[e * RS] = val[q][j][e];
+                        } else {
+                            *reinterpret_cast<TV*>(dst) = val[q][j];
+                        }
+                    }
+                }
+            }
         }
-      }
         __syncthreads();
         zero<T, 1, QP>(acc[q0 / QP]);
-        gemm<M, 1, QP>(a.P, NP, rb0, li, lg, acc[q0 / QP],
+        // one wave per SIMD: P fragments are requested four K blocks ahead
+        gemm<M, 1, QP, 4>(a.P, NP, rb0, li, lg, acc[q0 / QP],
                        [&](int qq, int k0) { return lds_vec<T, M::KL>(X + qq * AST + li * RS + k0); });
         __syncthreads();
     }

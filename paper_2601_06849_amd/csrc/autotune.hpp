@@ -15,7 +15,7 @@ namespace {
 template <typename T, int NC>
 std::vector<TileShape> outer_candidates(int NP) {
     std::vector<TileShape> v;
-    for (int rb : {1, 2, 4})
+    for (int rb : {1, 2, 4, 8})
         for (int cb : {1, 2})
             if (outer_shape_ok<T, NC>(NP, TileShape{rb, cb})) v.push_back(TileShape{rb, cb});
     return v;
@@ -24,7 +24,7 @@ std::vector<TileShape> outer_candidates(int NP) {
 template <typename T, int NC>
 std::vector<TileShape> x_candidates(int NP, long nlines) {
     std::vector<TileShape> v;
-    for (int rb : {1, 2, 4})
+    for (int rb : {1, 2, 4, 8})
         for (int cb : {1, 2, 4})
             if (x_shape_ok<T, NC>(NP, nlines, TileShape{rb, cb})) v.push_back(TileShape{rb, cb});
     return v;

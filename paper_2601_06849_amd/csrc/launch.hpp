@@ -87,7 +87,8 @@ int shape_threads(int NP, int rb) { return 64 * (NP / (16 * rb)); }
 
 template <typename T>
 bool shape_rows_ok(int NP, int rb) {
-    if (rb != 1 && rb != 2 && rb != 4) return false;
+    // eight row blocks per wave: FP32 state only (an FP64 tile would spill)
+    if (rb != 1 && rb != 2 && rb != 4 && !(rb == 8 && sizeof(T) == 4)) return false;
     if (NP % (16 * rb) != 0 || NP / (16 * rb) > kMaxWaves) return false;
     return !(rb == 4 && shape_threads(NP, rb) <= 512 && sizeof(T) != 4);
 }
@@ -97,7 +98,7 @@ bool outer_shape_ok(int NP, TileShape t) {
     if (!shape_rows_ok<T>(NP, t.rb)) return false;
     if (t.cb == 2) {
         if (t.rb >= 2 && shape_threads(NP, t.rb) > 512) return false;
-        if (t.rb == 4 && sizeof(T) != 4) return false;
+        if ((t.rb == 4 && sizeof(T) != 4) || t.rb == 8) return false;
     } else if (t.cb != 1) {
         return false;
     }
@@ -109,7 +110,7 @@ bool x_shape_ok(int NP, long nlines, TileShape t) {
     if (!shape_rows_ok<T>(NP, t.rb)) return false;
     if (t.cb == 2 || t.cb == 4) {
         if (t.rb >= 2 && shape_threads(NP, t.rb) > 512) return false;
-        if (t.rb == 4 && (t.cb == 4 || sizeof(T) != 4)) return false;
+        if ((t.rb == 4 && (t.cb == 4 || sizeof(T) != 4)) || t.rb == 8) return false;
         if (t.cb == 4 && !(sizeof(T) == 4 && NC == 1)) return false;
     } else if (t.cb != 1) {
         return false;
@@ -216,6 +217,12 @@ etd_status launch_outer_group_k(const Group<OuterArgs>& g, int NP, hipStream_t s
 template <typename T, int NC, typename L>
 etd_status outer_by_shape(int NP, TileShape t, L&& launch) {
     const bool small = shape_threads(NP, t.rb) <= 512;
+    if (t.rb == 8) {
+        if constexpr (sizeof(T) == 4)
+            return launch(std::integral_constant<int, 8>{}, std::integral_constant<int, 1>{},
+                          std::integral_constant<int, 512>{});
+        return fail(ETD_EUNSUPPORTED, "tile shape not available at this precision");
+    }
     if (t.rb == 1)
         return t.cb == 2 ? launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{},
                                   std::integral_constant<int, 1024>{})
@@ -302,6 +309,12 @@ etd_status launch_x_group_k(const Group<XArgs>& g, int NP, hipStream_t s) {
 template <typename T, int NC, typename L>
 etd_status x_by_shape(int NP, TileShape t, L&& launch) {
     const bool small = shape_threads(NP, t.rb) <= 512;
+    if (t.rb == 8) {
+        if constexpr (sizeof(T) == 4)
+            return launch(std::integral_constant<int, 8>{}, std::integral_constant<int, 1>{},
+                          std::integral_constant<int, 512>{});
+        return fail(ETD_EUNSUPPORTED, "tile shape not available at this precision");
+    }
     if (t.rb == 1) {
         if (t.cb == 4) {
             if constexpr (sizeof(T) == 4 && NC == 1)

@@ -47,8 +47,21 @@ __device__ __forceinline__ T react_coupled(const RxnArgs& r, int comp, T mine, T
 // of T (the contracted index contiguous, so a lane's B fragment is one
 // vector read), first the inputs (and f of them), then the scaled spectral
 // coefficients.
+// threadIdx.x behind an empty asm statement.  Inside a persistent loop the
+// tile functions then recompute their per-thread addressing for every tile
+// instead of having it hoisted out of the loop and held in vector registers
+// for the whole launch (which makes the 1024-thread tiles spill).
+__device__ __forceinline__ int tile_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // One thread's share of an outer tile's global inputs: ITER 16-byte vectors
 // of each loaded array (the workgroup has exactly 4 NP / RB threads).
+// Stage inputs and outputs are touched once per stage, so their loads and
+// stores carry the non-temporal hint; L2 then favours P, which every tile
+// reads again.
 template <typename M, int NC, bool FIRST, int RB, int CB>
 struct OuterRegs {
     typedef typename Vec16<typename M::elem>::type TV;
@@ -69,19 +82,20 @@ __device__ __forceinline__ void outer_load(const OuterArgs& a, long tile, OuterR
     const long gbase = (tile / a.ncb) * a.sb + long(tile % a.ncb) * NCOL;
     const T* __restrict__ in0 = static_cast<const T*>(a.in0);
     const T* __restrict__ in1 = static_cast<const T*>(a.in1);
+    const int tid = tile_tid();
 #pragma unroll
     for (int i = 0; i < OuterRegs<M, NC, FIRST, RB, CB>::ITER; ++i) {
-        const int v = threadIdx.x + i * blockDim.x;
+        const int v = tid + i * blockDim.x;
         if (v >= nvec) break;
         const int k = v / VPR, j0 = (v - k * VPR) * VN;
         const long gi = gbase + long(k) * a.sk + j0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            g.v[i][c] = *reinterpret_cast<const TV*>(in0 + gi + c * a.sc);
-            if constexpr (!FIRST) g.v[i][NC + c] = *reinterpret_cast<const TV*>(in1 + gi + c * a.sc);
+            g.v[i][c] = __builtin_nontemporal_load(reinterpret_cast<const TV*>(in0 + gi + c * a.sc));
+            if constexpr (!FIRST) g.v[i][NC + c] = __builtin_nontemporal_load(reinterpret_cast<const TV*>(in1 + gi + c * a.sc));
         }
         if constexpr (FIRST && NC == 1)
-            if (a.other) g.other[i] = *reinterpret_cast<const TV*>(static_cast<const T*>(a.other) + gi);
+            if (a.other) g.other[i] = __builtin_nontemporal_load(reinterpret_cast<const TV*>(static_cast<const T*>(a.other) + gi));
     }
 }
 
@@ -101,9 +115,10 @@ __device__ __forceinline__ void outer_store(const OuterArgs& a, long tile, const
     const int AST = NCOL * RS;
     const int nvec = NP * VPR;
     const int cb = int(tile % a.ncb);
+    const int tid = tile_tid();
 #pragma unroll
     for (int i = 0; i < OuterRegs<M, NC, FIRST, RB, CB>::ITER; ++i) {
-        const int v = threadIdx.x + i * blockDim.x;
+        const int v = tid + i * blockDim.x;
         if (v >= nvec) break;
         const int k = v / VPR, j0 = (v - k * VPR) * VN;
         if constexpr (FIRST) {
@@ -169,7 +184,7 @@ __device__ __forceinline__ void outer_compute(const OuterArgs& a, long tile) {
     const int NP = a.NP;
     const int RS = NP + 16 / int(sizeof(T));     // LDS stride between columns
     const int AST = NCOL * RS;
-    const int tid = threadIdx.x;
+    const int tid = tile_tid();
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
@@ -228,7 +243,7 @@ __device__ __forceinline__ void outer_compute(const OuterArgs& a, long tile) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = 16 * (rb0 + r) + M::row(lg, e);
-                o[long(row) * a.sk] = res[r][qq][e] + acc[r][qq][e];
+                __builtin_nontemporal_store(res[r][qq][e] + acc[r][qq][e], &o[long(row) * a.sk]);
             }
         }
 }
@@ -290,15 +305,16 @@ __device__ __forceinline__ void x_load(const XArgs& a, long tile, XRegs<M, NC, R
     const long base = tile * 16 * CB * long(a.NP);
     const T* __restrict__ w3 = static_cast<const T*>(a.w3);
     const T* __restrict__ w4 = static_cast<const T*>(a.w4);
+    const int tid = tile_tid();
 #pragma unroll
     for (int i = 0; i < XRegs<M, NC, RB, CB>::ITER; ++i) {
-        const int v = threadIdx.x + i * blockDim.x;
+        const int v = tid + i * blockDim.x;
         if (v >= nvec) break;
         const long gi = base + long(v) * VN;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            g.v[i][c] = *reinterpret_cast<const TV*>(w3 + c * a.sc + gi);
-            g.v[i][NC + c] = *reinterpret_cast<const TV*>(w4 + c * a.sc + gi);
+            g.v[i][c] = __builtin_nontemporal_load(reinterpret_cast<const TV*>(w3 + c * a.sc + gi));
+            g.v[i][NC + c] = __builtin_nontemporal_load(reinterpret_cast<const TV*>(w4 + c * a.sc + gi));
         }
     }
 }
@@ -316,9 +332,10 @@ __device__ __forceinline__ void x_store(const XArgs& a, const XRegs<M, NC, RB, C
     const int AST = 16 * CB * RS;
     const int nvec = 16 * CB * NP / VN;
     const int vpl = NP / VN;
+    const int tid = tile_tid();
 #pragma unroll
     for (int i = 0; i < XRegs<M, NC, RB, CB>::ITER; ++i) {
-        const int v = threadIdx.x + i * blockDim.x;
+        const int v = tid + i * blockDim.x;
         if (v >= nvec) break;
         const int j = v / vpl, x = (v - j * vpl) * VN;
 #pragma unroll
@@ -345,7 +362,7 @@ __device__ __forceinline__ void x_compute(const XArgs& a, long tile) {
     const int NP = a.NP;
     const int RS = NP + 16 / int(sizeof(T));
     const int AST = NL * RS;
-    const int tid = threadIdx.x;
+    const int tid = tile_tid();
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
@@ -461,7 +478,7 @@ __device__ __forceinline__ void x_compute(const XArgs& a, long tile) {
                 T* o = out + c * a.sc + line * NP + 16 * (rb0 + r);
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    o[M::row(lg, e)] = V[r][c * CB + cb][e] + tau * acc[r][c * CB + cb][e];
+                    __builtin_nontemporal_store(V[r][c * CB + cb][e] + tau * acc[r][c * CB + cb][e], &o[M::row(lg, e)]);
             }
     }
 }
@@ -718,12 +735,35 @@ struct Group {
     int k;               // the stage's time is t0 + k tau_i
 };
 
+// The descriptor table is read-only for the whole launch and every address
+// into it is uniform over the workgroup: read through the constant address
+// space it is fetched with scalar loads, and an instance's arguments then sit
+// in scalar registers, as a plain launch's kernel arguments do, instead of
+// taking vector registers from the tile body.
+template <typename X>
+__device__ __forceinline__ const __attribute__((address_space(4))) X* as_constant(const X* p) {
+    return (const __attribute__((address_space(4))) X*)(p);
+}
+
+// A trivially copyable struct read word by word through the constant space.
+template <typename X>
+__device__ __forceinline__ X load_constant(const X* p) {
+    static_assert(std::is_trivially_copyable<X>::value && sizeof(X) % 4 == 0, "word-wise copy");
+    X out;
+    const auto src = as_constant(reinterpret_cast<const unsigned*>(p));
+    unsigned* dst = reinterpret_cast<unsigned*>(&out);
+#pragma unroll
+    for (unsigned k = 0; k < sizeof(X) / 4; ++k) dst[k] = src[k];
+    return out;
+}
+
 template <typename A>
 __device__ __forceinline__ int group_instance(const Group<A>& g, long tile) {
+    const auto start = as_constant(g.start);
     int lo = 0, hi = g.n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (g.start[mid] <= tile) lo = mid;
+        if (start[mid] <= tile) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -737,9 +777,9 @@ template <typename M, int NC, bool FIRST, int RB, int CB, int MAXT>
 __global__ __launch_bounds__(MAXT) void outer_group(Group<OuterArgs> g) {
     for (long t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
         const int i = group_instance(g, t);
-        OuterArgs a = g.args[i];
+        OuterArgs a = load_constant(g.args + i);
         group_time(a.rxn, g.t0, g.k);
-        outer_tile<M, NC, FIRST, RB, CB>(a, t - g.start[i]);
+        outer_tile<M, NC, FIRST, RB, CB>(a, t - as_constant(g.start)[i]);
         __syncthreads();   // the next tile restages the LDS
     }
 }
@@ -748,9 +788,9 @@ template <typename M, int NC, int RB, int CB, int MAXT>
 __global__ __launch_bounds__(MAXT) void x_group(Group<XArgs> g) {
     for (long t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
         const int i = group_instance(g, t);
-        XArgs a = g.args[i];
+        XArgs a = load_constant(g.args + i);
         group_time(a.rxn, g.t0, g.k);
-        x_tile<M, NC, RB, CB>(a, t - g.start[i]);
+        x_tile<M, NC, RB, CB>(a, t - as_constant(g.start)[i]);
         __syncthreads();
     }
 }

@@ -43,7 +43,7 @@ def valid_shapes(etd, st, d):
     """Tile shapes accepted for direction d (others at their current choice)."""
     cur = st.tiles()
     out = []
-    for rb in (2, 4):
+    for rb in (2, 4, 8):
         for cb in (1, 2, 4):
             trial = list(cur)
             trial[d] = (rb, cb)

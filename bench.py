@@ -19,7 +19,9 @@ adjoint leg: one gradient of 1/2||u(T) - u_target||^2 through N steps of the
 batch: default tiles, autotuned tiles and a captured HIP graph; 0 skips it),
 --latency-steps N (the 63^2 Fisher-KPP case, eager calls vs a graph),
 --exact-steps N (the headline workload with the exact-exponential factors
-e^{-z}, phi_1, phi_2 in place of the Pade ones, FP64).
+e^{-z}, phi_1, phi_2 in place of the Pade ones, FP64), --fhn2d-steps N (the
+2-D coupled FitzHugh-Nagumo workload, 511^2 x 2 components, FP64 and FP32
+from the same u0; 0 skips it).
 """
 import argparse
 import hashlib
@@ -59,6 +61,7 @@ def parse():
     ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--latency-steps", type=int, default=100)
     ap.add_argument("--exact-steps", type=int, default=50)
+    ap.add_argument("--fhn2d-steps", type=int, default=200)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     return ap.parse_args()
@@ -235,6 +238,35 @@ def latency_leg(etd, torch, W, nsteps):
             "graph_us_per_step": 1e6 * graph / nsteps}
 
 
+def fhn2d_leg(etd, torch, W, nsteps):
+    """2-D coupled FitzHugh-Nagumo, 511^2 x 2 components (the product-parallel
+    2-D path): FP64 and FP32 over the same steps from the same u0, timed
+    without per-stage events (a step is only about 0.1-0.2 ms).  Useful work
+    is 18 n^3 flops per component and step (nine mode products)."""
+    out = {"workload": "fhn2d_n511", "steps": nsteps}
+    final = {}
+    for prec in ("fp64", "fp32"):
+        wl = W.fhn2d(precision=prec)
+        n = wl.problem.n[0]
+        st = etd.Stepper(wl.problem)
+        u0 = wl.u0()
+        st.advance(st.field(u0), 5)
+        u = st.field(u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.advance(u, nsteps)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        st.close()
+        useful = 18.0 * n ** 3 * wl.problem.ncomp * nsteps
+        out[prec] = {"ms_per_step": 1e3 * sec / nsteps, "value": n * n * nsteps / sec,
+                     "useful_tflops": useful / sec / 1e12, "frac_of_peak": useful / sec / 1e12 / PEAK_TFLOPS[prec]}
+        final[prec] = u
+    out["fp32"]["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
+    out["fp32"]["rel_l2_vs_fp64"] = float((final["fp32"].double() - final["fp64"]).norm() / final["fp64"].norm())
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -313,6 +345,9 @@ def main():
         out["exact_exponential"] = {"ms_per_step": 1e3 * sec_e / args.exact_steps,
                                     "value": npts * args.exact_steps / sec_e, "steps": args.exact_steps,
                                     "rel_l2_vs_pade02": float((u_e - u_p).norm() / u_p.norm())}
+
+    if args.fhn2d_steps > 0:
+        out["fhn2d"] = fhn2d_leg(etd, torch, W, args.fhn2d_steps)
 
     if not args.no_cpu_baseline:
         # the oracle as it stands, in chunks of --cpu-steps steps until about

@@ -59,9 +59,10 @@ __device__ __forceinline__ int tile_tid() {
 
 // One thread's share of an outer tile's global inputs: ITER 16-byte vectors
 // of each loaded array (the workgroup has exactly 4 NP / RB threads).
-// Stage inputs and outputs are touched once per stage, so their loads and
-// stores carry the non-temporal hint; L2 then favours P, which every tile
-// reads again.
+// Stage inputs are read once per stage, so their loads carry the
+// non-temporal hint and L2 favours P, which every tile reads again.  (The
+// scattered element stores of the outputs keep the default policy: with the
+// hint their partial lines reach HBM separately.)
 template <typename M, int NC, bool FIRST, int RB, int CB>
 struct OuterRegs {
     typedef typename Vec16<typename M::elem>::type TV;
@@ -243,7 +244,7 @@ __device__ __forceinline__ void outer_compute(const OuterArgs& a, long tile) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = 16 * (rb0 + r) + M::row(lg, e);
-                __builtin_nontemporal_store(res[r][qq][e] + acc[r][qq][e], &o[long(row) * a.sk]);
+                o[long(row) * a.sk] = res[r][qq][e] + acc[r][qq][e];
             }
         }
 }
@@ -478,7 +479,7 @@ __device__ __forceinline__ void x_compute(const XArgs& a, long tile) {
                 T* o = out + c * a.sc + line * NP + 16 * (rb0 + r);
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    __builtin_nontemporal_store(V[r][c * CB + cb][e] + tau * acc[r][c * CB + cb][e], &o[M::row(lg, e)]);
+                    o[M::row(lg, e)] = V[r][c * CB + cb][e] + tau * acc[r][c * CB + cb][e];
             }
     }
 }

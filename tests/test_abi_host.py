@@ -218,6 +218,14 @@ def test_tile_shapes_host_validation(etd):
                 etd.etd_plan_set_tiles(plan, bad)
             assert ei.value.status == etd.ETD_EUNSUPPORTED
         assert etd.etd_plan_tiles(plan) == [(4, 1), (2, 1), (4, 1)]
+        # eight row blocks per wave: one column block, FP32 states only
+        etd.etd_plan_set_tiles(plan, [(4, 1), (2, 1), (8, 1)])
+        assert etd.etd_plan_tiles(plan) == [(4, 1), (2, 1), (8, 1)]
+        for bad in ([(4, 1), (2, 1), (8, 2)], [(8, 2)], [(8, 4)]):
+            with pytest.raises(etd.EtdError) as ei:
+                etd.etd_plan_set_tiles(plan, bad)
+            assert ei.value.status == etd.ETD_EUNSUPPORTED
+        assert etd.etd_plan_tiles(plan) == [(4, 1), (2, 1), (8, 1)]
         etd.etd_plan_set_tiles(plan, [(0, 0)] * 3)
         assert etd.etd_plan_tiles(plan) == d
     finally:
@@ -226,10 +234,25 @@ def test_tile_shapes_host_validation(etd):
     plan = etd.etd_plan_create(p64)
     try:
         assert etd.etd_plan_tiles(plan) == [(1, 2), (1, 2), (1, 2)]
-        with pytest.raises(etd.EtdError):   # rb = 4 at <= 8 waves is built for FP32 states only
-            etd.etd_plan_set_tiles(plan, [(4, 1)])
+        for bad in ([(4, 1)], [(8, 1)]):   # rb = 4 at <= 8 waves and rb = 8: FP32 states only
+            with pytest.raises(etd.EtdError) as ei:
+                etd.etd_plan_set_tiles(plan, bad)
+            assert ei.value.status == etd.ETD_EUNSUPPORTED
     finally:
         etd.etd_plan_destroy(plan)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark is a one-GPU measurement: --gpus above 1 exits with a
+    message (before anything touches a device)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
 
 
 def test_batch_host_validation(etd):

@@ -39,7 +39,7 @@ extern "C" {
 typedef enum {
     ETD_OK = 0,
     ETD_EINVAL = -1,        /* invalid argument */
-    ETD_EUNSUPPORTED = -2,  /* valid problem this build cannot run (size limits) */
+    ETD_EUNSUPPORTED = -2,  /* valid problem the library cannot run (size limits) */
     ETD_EWORKSPACE = -3,    /* workspace missing, misaligned or too small */
     ETD_EHIP = -4,          /* HIP runtime error */
     ETD_ENONFINITE = -5     /* etd_compare found NaN or Inf in the field */

@@ -349,3 +349,30 @@ def test_exact_exponential_tables_match_block_expm(etd, oracle_mod):
                     assert np.abs((P * qv) @ P.T - ref[ell - 1]).max() < 1e-13
     finally:
         etd.etd_plan_destroy(plan)
+
+
+def test_missing_library_fails_loudly():
+    """Without the built HIP library the package raises; there is no fallback."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import paper_2601_06849_amd as m\n"
+            "m.LIB_PATH = '/nonexistent/libetdds.so'\n"
+            "try:\n    m.lib()\nexcept RuntimeError as e:\n    print('raised:', e)\nelse:\n    print('loaded')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.startswith("raised:") and "missing" in r.stdout
+
+
+def test_product_path_never_touches_the_oracle():
+    """The package (Python binding and HIP sources) neither imports nor links
+    the oracle: the two share no code."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.join(root, "paper_2601_06849_amd")
+    files = [os.path.join(pkg, f) for f in os.listdir(pkg) if f.endswith(".py")]
+    files += [os.path.join(pkg, "csrc", f) for f in os.listdir(os.path.join(pkg, "csrc"))]
+    for f in files:
+        text = open(f).read()
+        assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
+        assert "etdo" not in text, f
+        assert "oracle/" not in text, f

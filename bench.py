@@ -241,8 +241,9 @@ def latency_leg(etd, torch, W, nsteps):
 def fhn2d_leg(etd, torch, W, nsteps):
     """2-D coupled FitzHugh-Nagumo, 511^2 x 2 components (the product-parallel
     2-D path): FP64 and FP32 over the same steps from the same u0, timed
-    without per-stage events (a step is only about 0.1-0.2 ms).  Useful work
-    is 18 n^3 flops per component and step (nine mode products)."""
+    without per-stage events (a step is only about 0.1-0.2 ms), then the same
+    steps replayed from a captured HIP graph.  Useful work is 18 n^3 flops per
+    component and step (nine mode products)."""
     out = {"workload": "fhn2d_n511", "steps": nsteps}
     final = {}
     for prec in ("fp64", "fp32"):
@@ -257,11 +258,22 @@ def fhn2d_leg(etd, torch, W, nsteps):
         st.advance(u, nsteps)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
+        final[prec] = u.clone()
+        # the same steps captured once in a HIP graph and replayed
+        s = torch.cuda.Stream()
+        g = st.capture(u, nsteps, s)
+        g.launch(s)
+        s.synchronize()
+        t0 = time.perf_counter()
+        g.launch(s)
+        s.synchronize()
+        gsec = time.perf_counter() - t0
+        g.close()
         st.close()
         useful = 18.0 * n ** 3 * wl.problem.ncomp * nsteps
         out[prec] = {"ms_per_step": 1e3 * sec / nsteps, "value": n * n * nsteps / sec,
-                     "useful_tflops": useful / sec / 1e12, "frac_of_peak": useful / sec / 1e12 / PEAK_TFLOPS[prec]}
-        final[prec] = u
+                     "useful_tflops": useful / sec / 1e12, "frac_of_peak": useful / sec / 1e12 / PEAK_TFLOPS[prec],
+                     "graph_ms_per_step": 1e3 * gsec / nsteps}
     out["fp32"]["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
     out["fp32"]["rel_l2_vs_fp64"] = float((final["fp32"].double() - final["fp64"]).norm() / final["fp64"].norm())
     return out

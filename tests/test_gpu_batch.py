@@ -260,3 +260,47 @@ def test_product_parallel_2d_matches_fused_stages(etd, precision, reaction):
     diff = np.abs(single - fused).max() / np.abs(fused).max()
     print(f"  max rel diff {diff:.2e}")
     assert diff <= (0.0 if precision == "fp64" else 1e-6) or np.array_equal(single, fused)
+
+
+def test_independent_plans_and_a_batch_on_concurrent_streams(etd):
+    """Plans share no mutable device state: two plans and a batch advanced in
+    interleaved calls on three streams give, bit for bit, what each gives
+    alone on the default stream."""
+    import torch
+    p3 = W.Problem(dim=3, n=(63, 40, 33), kappa=(0.02,), q=0.3, tau=0.01, reaction="fisher")
+    p2 = W.Problem(dim=2, n=(255, 127), kappa=(1e-3, 1e-4), tau=0.05, reaction="fhn_cubic", precision="fp32")
+    probs, u0s = mixed_batch("fp32")
+    u3 = W.initial_field(p3, "sine_noise", 5)
+    u2 = W.initial_field(p2, "fhn_patch", 6)
+
+    def alone():
+        a = etd.Stepper(p3)
+        b = etd.Stepper(p2)
+        c = etd.Batch(probs)
+        x, y, z = a.field(u3), b.field(u2), c.fields(u0s)
+        a.advance(x, 12)
+        b.advance(y, 12)
+        c.advance(z, 12)
+        torch.cuda.synchronize()
+        out = (host(x), host(y), [host(f) for f in z])
+        a.close(), b.close(), c.close()
+        return out
+
+    ref = alone()
+    a, b, c = etd.Stepper(p3), etd.Stepper(p2), etd.Batch(probs)
+    x, y, z = a.field(u3), b.field(u2), c.fields(u0s)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    for k in range(4):
+        with torch.cuda.stream(streams[0]):
+            a.advance(x, 3, 3 * k * p3.tau)
+        with torch.cuda.stream(streams[1]):
+            b.advance(y, 3, 3 * k * p2.tau)
+        with torch.cuda.stream(streams[2]):
+            c.advance(z, 3, 3 * k * 0.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(x), ref[0])
+    assert np.array_equal(host(y), ref[1])
+    for got, want in zip(z, ref[2]):
+        assert np.array_equal(host(got), want)
+    a.close(), b.close(), c.close()

@@ -113,7 +113,8 @@ etd_status resolve_tile(const Plan& pl, int d, TileShape t, TileShape& out) {
     const int NP = pl.np[d];
     const long nlines = long(pl.np[1]) * pl.np[2];
     if (t.rb == 0 && t.cb == 0) {
-        out = d == 0 ? default_x_for<M, NC>(NP, nlines) : default_outer_for<M, NC>(NP);
+        const long ncols16 = long(pl.np[0]) * pl.np[1] * pl.np[2] / NP / 16;
+        out = d == 0 ? default_x_for<M, NC>(NP, nlines) : default_outer_for<M, NC>(NP, ncols16);
         return ETD_OK;
     }
     const bool ok = d == 0 ? x_shape_ok<T, NC>(NP, nlines, t) : outer_shape_ok<T, NC>(NP, t);

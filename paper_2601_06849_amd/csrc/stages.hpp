@@ -505,8 +505,10 @@ __global__ __launch_bounds__(MAXT) void x_stage(XArgs a) {
 // its own over (row group) x (16-column tile) blocks, and the scalings, the
 // reaction and the increment-form residuals move into the epilogues; the
 // intermediates stay in L2/MALL (2 MB per field at 511^2).  Every output is
-// computed with the same operations in the same order as in the fused
-// stages.  The y stage takes two launches, the x stage four:
+// computed with the fused stages' operations in the same order, up to how the
+// compiler fuses a few epilogue multiply-adds (FP64 results are bitwise those
+// of the fused kernels; two-component FP32 ones differ by ~1e-7 relative).
+// The y stage takes two launches, the x stage four:
 //   YF: WC = dy .* (P U), WD = dy .* (P f(U))          (dy = Q1y - 1)
 //   YB: WA = U + P WC (= w3), WB = f(U) + P WD (= w4)
 //   X1: WC = d1 .* (P w3) + d2 .* (P w4)                (= c)

@@ -28,7 +28,8 @@ struct BatchGroup {
 
 struct Batch {
     std::vector<Plan> plans;
-    std::vector<size_t> base;         // workspace offset of each instance's region
+    std::vector<size_t> base;         // workspace offset of each instance's region (its plan layout's 0)
+    std::vector<size_t> skip;         // leading table bytes the instance neither holds nor uploads
     std::vector<int> powner[3];       // instance whose P table instance i uses, per direction
     std::vector<BatchGroup> groups;
     int dim = 0, nc = 0, precision = 0;
@@ -52,12 +53,6 @@ size_t desc_bytes_of(const Batch& B) {
 }
 
 etd_status batch_layout(Batch& B) {
-    size_t off = 0;
-    B.base.resize(B.plans.size());
-    for (size_t i = 0; i < B.plans.size(); ++i) {
-        B.base[i] = off;
-        off = a256(off + B.plans[i].lay.total);
-    }
     for (int d = 0; d < 3; ++d) {
         B.powner[d].assign(B.plans.size(), 0);
         for (size_t i = 0; i < B.plans.size(); ++i) {
@@ -65,6 +60,25 @@ etd_status batch_layout(Batch& B) {
             while (j < i && !(B.plans[j].n[d] == B.plans[i].n[d] && B.plans[j].np[d] == B.plans[i].np[d])) ++j;
             B.powner[d][i] = int(j);
         }
+    }
+    // The P tables lead a plan's layout.  An instance that takes every
+    // direction's P from an earlier instance holds none of them: its region
+    // starts at its first table after P, and its (unused) P offsets fall on
+    // earlier regions, which it never reads or writes.  The owner of an
+    // extent comes first and keeps its whole region, so the base stays >= 0.
+    size_t off = 0;
+    B.base.resize(B.plans.size());
+    B.skip.assign(B.plans.size(), 0);
+    for (size_t i = 0; i < B.plans.size(); ++i) {
+        const Plan& pl = B.plans[i];
+        bool borrows_all = true;
+        for (int d = 0; d < pl.dim; ++d) borrows_all = borrows_all && B.powner[d][i] != int(i);
+        // (earlier regions hold the owners' P of the same sizes, so off >=
+        // pl.lay.diag whenever every direction is borrowed; kept as a check)
+        const size_t skip = borrows_all && off >= pl.lay.diag ? pl.lay.diag : 0;
+        B.skip[i] = skip;
+        B.base[i] = off - skip;
+        off = a256(off + pl.lay.total - skip);
     }
     for (size_t i = 0; i < B.plans.size(); ++i) {
         const Plan& pl = B.plans[i];

@@ -342,7 +342,9 @@ etd_status etd_batch_upload(etd_batch* batch, void* ws, size_t bytes, void* stre
     char* w = static_cast<char*>(ws);
     for (size_t i = 0; i < B.plans.size(); ++i) {
         const Plan& pl = B.plans[i];
-        HIP_TRY(hipMemcpyAsync(w + B.base[i], pl.image.data(), pl.table_bytes, hipMemcpyHostToDevice, s),
+        const size_t skip = B.skip[i];   // P tables borrowed from an earlier instance
+        HIP_TRY(hipMemcpyAsync(w + B.base[i] + skip, pl.image.data() + skip, pl.table_bytes - skip,
+                               hipMemcpyHostToDevice, s),
                 "table upload");
         HIP_TRY(hipMemsetAsync(w + B.base[i] + pl.lay.field[0], 0, pl.lay.total - pl.lay.field[0], s),
                 "workspace clear");

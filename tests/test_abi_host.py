@@ -376,3 +376,24 @@ def test_product_path_never_touches_the_oracle():
         assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
         assert "etdo" not in text, f
         assert "oracle/" not in text, f
+
+
+def test_batch_holds_one_p_per_extent(etd):
+    """Instances that borrow every direction's P hold no copy: a batch of k
+    equal instances needs k plan workspaces minus (k - 1) P tables."""
+    p = W.Problem(dim=2, n=(255, 255), kappa=(0.01,), tau=0.01, reaction="fisher", precision="fp32")
+    plan = etd.etd_plan_create(p)
+    try:
+        single = etd.etd_plan_workspace_bytes(plan)
+    finally:
+        etd.etd_plan_destroy(plan)
+    p_bytes = 2 * 256 * 256 * 4          # P_x and P_y of one instance
+    for k in (1, 3):
+        b = etd.etd_batch_create([p] * k)
+        try:
+            total = etd.etd_batch_workspace_bytes(b)
+        finally:
+            etd.etd_batch_destroy(b)
+        assert total % 256 == 0
+        # k regions, the last k - 1 without their P tables, plus the descriptor table (< 64 KiB here)
+        assert k * single - (k - 1) * p_bytes <= total < k * single - (k - 1) * p_bytes + 65536

@@ -179,7 +179,8 @@ etd_status etd_plan_autotune(etd_plan* plan, void* workspace_dev, void* stream);
  * its instances' tiles (a descriptor table in the workspace gives each
  * instance's buffers and tables); groups run on streams of their own,
  * created by the first upload, forked from and joined back to `stream`.
- * Instances of equal extent share one eigenvector table.
+ * Instances of equal extent share one eigenvector table; an instance that
+ * finds every direction's table in an earlier instance holds no copy.
  *  - create: ETD_EINVAL as etd_plan_create (message names the instance) or
  *    when instances differ in dim/ncomp/precision; ETD_EUNSUPPORTED for a
  *    two-component instance whose joint tile exceeds the LDS.

@@ -107,3 +107,39 @@ def test_gpu_second_order_in_time_at_benchmark_grid(etd, precision):
     eoc = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     print(f"  {precision}: E = {errs}, EOC = {eoc}")
     assert all(1.8 < e < 2.3 for e in eoc), (errs, eoc)
+
+
+def _q(ell, x):
+    """The P_{0,2} factors Q1 = 2/D, Q2 = (x+2)/D, Q3 = (x+1)/D, D = x^2+2x+2
+    (Sec. 3.1), as plain scalars."""
+    den = x * x + 2 * x + 2
+    return {1: 2.0, 2: x + 2, 3: x + 1}[ell] / den
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-6), ("bf16x6", 2e-6)])
+def test_gpu_linear_mode_amplification_at_benchmark_grid(etd, precision, tol):
+    """f = c u on a joint sine mode of the 255^3 grid is an eigenvector of
+    every operator of the step, so one step multiplies it by the closed-form
+    factor (a_d = Q1(tau lambda_d), A = a_z a_y, b = Q2(tau lambda_x),
+    e = Q3(tau lambda_x)): W = (a_x A + tau c b A) U, U+ = W + tau e c (W - A U)."""
+    import torch
+    c = -2.3
+    p = W.Problem(dim=3, n=(255, 255, 255), kappa=(0.005,), q=0.5, tau=0.005, reaction="linear",
+                  rxn_param=(c,), precision=precision)
+    js = (3, 17, 200)
+    vecs = [np.sin(js[d] * math.pi * np.arange(1, 256) / 256.0) for d in range(3)]
+    U = np.einsum("k,j,i->kji", vecs[2], vecs[1], vecs[0])[None]
+    tl = [p.tau * (p.kappa[0] * 4 / p.h(d) ** 2 * math.sin(js[d] * math.pi / 512.0) ** 2 + p.q / 3)
+          for d in range(3)]
+    ax, A = _q(1, tl[0]), _q(1, tl[1]) * _q(1, tl[2])
+    Wf = ax * A + p.tau * c * _q(2, tl[0]) * A
+    amp = Wf + p.tau * _q(3, tl[0]) * c * (Wf - A)
+    st = etd.Stepper(p)
+    u = st.field(U)
+    st.advance(u, 1)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy().astype(np.float64)
+    st.close()
+    err = float(np.abs(got - amp * U).max())
+    print(f"  {precision}: amplification {amp:.15f}, max error {err:.2e}")
+    assert err <= tol

@@ -1,7 +1,7 @@
 // Tile-shape autotuning.
 //
-// Part of libetdds: included, in order, by etdds.hip only (one translation
-// unit); every definition has internal linkage.
+// Part of libetdds: included, in order, by library.hpp (each translation
+// unit that includes it holds its own copy); internal linkage throughout.
 #pragma once
 
 namespace {
@@ -121,19 +121,6 @@ etd_status resolve_tile(const Plan& pl, int d, TileShape t, TileShape& out) {
     if (!ok) return fail(ETD_EUNSUPPORTED, "tile shape not valid for this direction");
     out = t;
     return ETD_OK;
-}
-
-etd_status resolve_tile_any(const Plan& pl, int d, TileShape t, TileShape& out) {
-    switch (pl.prob.precision) {
-    case ETD_FP64:
-        return pl.nc == 1 ? resolve_tile<NativeMma<double>, 1>(pl, d, t, out)
-                          : resolve_tile<NativeMma<double>, 2>(pl, d, t, out);
-    case ETD_FP32:
-        return pl.nc == 1 ? resolve_tile<NativeMma<float>, 1>(pl, d, t, out)
-                          : resolve_tile<NativeMma<float>, 2>(pl, d, t, out);
-    default:
-        return pl.nc == 1 ? resolve_tile<Bf16x6Mma, 1>(pl, d, t, out) : resolve_tile<Bf16x6Mma, 2>(pl, d, t, out);
-    }
 }
 
 }  // namespace

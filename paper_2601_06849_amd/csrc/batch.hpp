@@ -1,7 +1,7 @@
 // Batches of independent instances (grouped persistent launches).
 //
-// Part of libetdds: included, in order, by etdds.hip only (one translation
-// unit); every definition has internal linkage.
+// Part of libetdds: included, in order, by library.hpp (each translation
+// unit that includes it holds its own copy); internal linkage throughout.
 #pragma once
 
 namespace {
@@ -14,33 +14,6 @@ namespace {
 // its instances' tiles, on a stream of its own, so groups of different shapes
 // overlap on the device.  Instances of equal extent share one P table.
 // ---------------------------------------------------------------------------
-
-struct BatchGroup {
-    int np[3] = {1, 1, 1};
-    std::vector<int> inst;            // instance indices
-    TileShape tile[3];                // per direction
-    size_t oargs[2] = {0, 0}, ostart[2] = {0, 0};   // descriptor offsets (bytes into the workspace)
-    size_t xargs = 0, xstart = 0;
-    long otiles[2] = {0, 0}, xtiles = 0;
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
-};
-
-struct Batch {
-    std::vector<Plan> plans;
-    std::vector<size_t> base;         // workspace offset of each instance's region (its plan layout's 0)
-    std::vector<size_t> skip;         // leading table bytes the instance neither holds nor uploads
-    std::vector<int> powner[3];       // instance whose P table instance i uses, per direction
-    std::vector<BatchGroup> groups;
-    int dim = 0, nc = 0, precision = 0;
-    size_t desc = 0, desc_bytes = 0, total = 0;
-    char* uploaded = nullptr;         // the workspace the descriptors point into
-    hipEvent_t fork = nullptr;
-    // Bumped whenever the descriptors change shape or address; a graph
-    // captured before then refuses to launch.  Shared with the graphs so that
-    // it outlives the batch (0 = batch destroyed).
-    std::shared_ptr<unsigned> generation = std::make_shared<unsigned>(1);
-};
 
 size_t desc_bytes_of(const Batch& B) {
     size_t n = 0;

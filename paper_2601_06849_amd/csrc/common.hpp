@@ -1,13 +1,11 @@
 // Error reporting and the matrix-core policies of the mode products (FP64/FP32
 // MFMA and split BF16), with the vector and LDS helpers they use.
 //
-// Part of libetdds: included, in order, by etdds.hip only (one translation
-// unit); every definition has internal linkage.
+// Part of libetdds: included, in order, by library.hpp (each translation
+// unit that includes it holds its own copy); internal linkage throughout.
 #pragma once
 
 namespace {
-
-thread_local std::string g_err;
 
 etd_status fail(etd_status s, const std::string& m) {
     g_err = m;

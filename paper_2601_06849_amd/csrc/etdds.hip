@@ -20,54 +20,20 @@
 // or 16 columns (outer stages) over the whole contracted direction, so the
 // forward product, the Hadamard scaling and the backward product stay on chip.
 //
-// This file holds the C ABI; the kernels and host drivers are in the headers
-// it includes, in dependency order: common (errors, matrix-core policies),
-// reactions, gemm (the K-loop), stages (forward kernels), adjoint_kernels,
-// field_kernels (pack/unpack, reductions), launch (tile shapes, launchers,
-// step drivers), adjoint (checkpointed reverse sweep), autotune, batch and
-// graphs.
-#include <hip/hip_runtime.h>
+// This file holds the C ABI.  The kernels and host drivers are in the headers
+// of library.hpp; each mode-product precision instantiates them in a
+// translation unit of its own (kern_<precision>.hip), reached here through
+// its table of entry functions (PrecisionOps).
+#include "library.hpp"
 
-#include <algorithm>
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <memory>
-#include <mutex>
-#include <string>
-#include <type_traits>
-#include <vector>
-
-#include "etdds.h"
-#include "plan.hpp"
-
-using namespace etdds;
-
-// Optional per-stage timing: HIP events recorded on the caller's stream
-// around every stage launch (diagnostics; not thread-safe).
-struct StageTimer {
-    bool on = false;
-    std::vector<hipEvent_t> pool;    // reusable events
-    size_t used = 0;                 // events recorded since the last read
-    std::vector<int> kind;           // stage kind of interval i = (ev[2i], ev[2i+1])
-};
+namespace etdds {
+thread_local std::string g_err;
+}  // namespace etdds
 
 struct etd_plan {
     Plan p;
     mutable StageTimer timer;
 };
-
-#include "common.hpp"
-#include "reactions.hpp"
-#include "gemm.hpp"
-#include "stages.hpp"
-#include "adjoint_kernels.hpp"
-#include "field_kernels.hpp"
-#include "launch.hpp"
-#include "adjoint.hpp"
-#include "autotune.hpp"
-#include "batch.hpp"
-#include "graphs.hpp"
 
 struct etd_batch {
     Batch b;
@@ -82,18 +48,20 @@ struct etd_graph {
 
 namespace {
 
-etd_status batch_dispatch_advance(Batch& B, void* const* u, double t0, int nsteps, char* ws, hipStream_t s) {
-    switch (B.precision) {
-    case ETD_FP64:
-        return B.nc == 1 ? batch_advance_t<NativeMma<double>, 1>(B, u, t0, nsteps, ws, s)
-                         : batch_advance_t<NativeMma<double>, 2>(B, u, t0, nsteps, ws, s);
-    case ETD_FP32:
-        return B.nc == 1 ? batch_advance_t<NativeMma<float>, 1>(B, u, t0, nsteps, ws, s)
-                         : batch_advance_t<NativeMma<float>, 2>(B, u, t0, nsteps, ws, s);
-    default:
-        return B.nc == 1 ? batch_advance_t<Bf16x6Mma, 1>(B, u, t0, nsteps, ws, s)
-                         : batch_advance_t<Bf16x6Mma, 2>(B, u, t0, nsteps, ws, s);
+const PrecisionOps& ops_for(int precision) {
+    switch (precision) {
+    case ETD_FP64: return ops_fp64();
+    case ETD_FP32: return ops_fp32();
+    default: return ops_bf16x6();
     }
+}
+
+etd_status batch_dispatch_advance(Batch& B, void* const* u, double t0, int nsteps, char* ws, hipStream_t s) {
+    return ops_for(B.precision).batch_advance(B, u, t0, nsteps, ws, s);
+}
+
+etd_status resolve_tile_any(const Plan& pl, int d, TileShape t, TileShape& out) {
+    return ops_for(pl.prob.precision).resolve_tile(pl, d, t, out);
 }
 
 etd_status batch_check(const Batch& B, void* const* u, int nsteps, const void* ws) {
@@ -161,11 +129,7 @@ etd_status etd_advance(const etd_plan* plan, void* u, double t0, int nsteps, voi
     if (nsteps == 0) return ETD_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(ws);
-    switch (plan->p.prob.precision) {
-    case ETD_FP64: return advance_m<NativeMma<double>>(plan->p, plan->timer, u, t0, nsteps, w, s);
-    case ETD_FP32: return advance_m<NativeMma<float>>(plan->p, plan->timer, u, t0, nsteps, w, s);
-    default: return advance_m<Bf16x6Mma>(plan->p, plan->timer, u, t0, nsteps, w, s);
-    }
+    return ops_for(plan->p.prob.precision).advance(plan->p, plan->timer, u, t0, nsteps, w, s);
 }
 
 etd_status etd_adjoint_workspace_bytes(const etd_plan* plan, int nsteps, size_t* bytes) {
@@ -194,17 +158,7 @@ etd_status etd_adjoint(const etd_plan* plan, const void* u0, double t0, int nste
     char* w = static_cast<char*>(ws);
     char* a = static_cast<char*>(adj_ws);
     const Plan& pl = plan->p;
-    switch (pl.prob.precision) {
-    case ETD_FP64:
-        return pl.nc == 1 ? adjoint_t<NativeMma<double>, 1>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s)
-                          : adjoint_t<NativeMma<double>, 2>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s);
-    case ETD_FP32:
-        return pl.nc == 1 ? adjoint_t<NativeMma<float>, 1>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s)
-                          : adjoint_t<NativeMma<float>, 2>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s);
-    default:
-        return pl.nc == 1 ? adjoint_t<Bf16x6Mma, 1>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s)
-                          : adjoint_t<Bf16x6Mma, 2>(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, L, s);
-    }
+    return ops_for(pl.prob.precision).adjoint(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, s);
 }
 
 etd_status etd_plan_autotune(etd_plan* plan, void* ws, void* stream) {
@@ -216,16 +170,7 @@ etd_status etd_plan_autotune(etd_plan* plan, void* ws, void* stream) {
     Plan& pl = plan->p;
     const bool timing = plan->timer.on;
     plan->timer.on = false;
-    switch (pl.prob.precision) {
-    case ETD_FP64:
-        st = pl.nc == 1 ? autotune_plan_t<NativeMma<double>, 1>(pl, w, s) : autotune_plan_t<NativeMma<double>, 2>(pl, w, s);
-        break;
-    case ETD_FP32:
-        st = pl.nc == 1 ? autotune_plan_t<NativeMma<float>, 1>(pl, w, s) : autotune_plan_t<NativeMma<float>, 2>(pl, w, s);
-        break;
-    default:
-        st = pl.nc == 1 ? autotune_plan_t<Bf16x6Mma, 1>(pl, w, s) : autotune_plan_t<Bf16x6Mma, 2>(pl, w, s);
-    }
+    st = ops_for(pl.prob.precision).autotune(pl, w, s);
     plan->timer.on = timing;
     return st;
 }
@@ -374,14 +319,7 @@ etd_status etd_batch_autotune(etd_batch* batch, void* ws, void* stream) {
     if (!ws || ws != B.uploaded) return fail(ETD_EWORKSPACE, "workspace is not the one the batch was uploaded to");
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(ws);
-    switch (B.precision) {
-    case ETD_FP64:
-        return B.nc == 1 ? batch_autotune_t<NativeMma<double>, 1>(B, w, s) : batch_autotune_t<NativeMma<double>, 2>(B, w, s);
-    case ETD_FP32:
-        return B.nc == 1 ? batch_autotune_t<NativeMma<float>, 1>(B, w, s) : batch_autotune_t<NativeMma<float>, 2>(B, w, s);
-    default:
-        return B.nc == 1 ? batch_autotune_t<Bf16x6Mma, 1>(B, w, s) : batch_autotune_t<Bf16x6Mma, 2>(B, w, s);
-    }
+    return ops_for(B.precision).batch_autotune(B, w, s);
 }
 
 etd_status etd_batch_tiles(const etd_batch* batch, int instance, int tiles[6]) {
@@ -433,11 +371,7 @@ etd_status etd_graph_capture(const etd_plan* plan, void* u, double t0, int nstep
     plan->timer.on = false;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "graph capture begin");
     char* w = static_cast<char*>(ws);
-    switch (plan->p.prob.precision) {
-    case ETD_FP64: st = advance_m<NativeMma<double>>(plan->p, plan->timer, u, t0, nsteps, w, s); break;
-    case ETD_FP32: st = advance_m<NativeMma<float>>(plan->p, plan->timer, u, t0, nsteps, w, s); break;
-    default: st = advance_m<Bf16x6Mma>(plan->p, plan->timer, u, t0, nsteps, w, s);
-    }
+    st = ops_for(plan->p.prob.precision).advance(plan->p, plan->timer, u, t0, nsteps, w, s);
     plan->timer.on = timing;
     hipGraph_t g;
     st = end_capture(s, st, g);

@@ -1,7 +1,7 @@
 // Host-side launch plumbing: tile shapes, launchers and the step drivers.
 //
-// Part of libetdds: included, in order, by etdds.hip only (one translation
-// unit); every definition has internal linkage.
+// Part of libetdds: included, in order, by library.hpp (each translation
+// unit that includes it holds its own copy); internal linkage throughout.
 #pragma once
 
 namespace {
@@ -79,10 +79,6 @@ hipError_t set_lds(K kernel, size_t bytes, size_t& done) {
 // single-component FP32-state systems, two for other FP32 states (a
 // two-component FP64 tile would spill).  An autotuned plan times every valid
 // shape instead.
-struct TileShape {
-    int rb = 0, cb = 0;   // rb == 0: use the default
-};
-
 int shape_threads(int NP, int rb) { return 64 * (NP / (16 * rb)); }
 
 template <typename T>

@@ -1,8 +1,8 @@
 // Pointwise source terms f(t, u) of the examples and workloads, and their
 // transposed Jacobians (for the adjoint).
 //
-// Part of libetdds: included, in order, by etdds.hip only (one translation
-// unit); every definition has internal linkage.
+// Part of libetdds: included, in order, by library.hpp (each translation
+// unit that includes it holds its own copy); internal linkage throughout.
 #pragma once
 
 namespace {

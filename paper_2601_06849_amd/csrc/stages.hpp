@@ -1,8 +1,8 @@
 // Forward stage kernels: the fused outer and x stages, the product-parallel
 // 2-D path, the grouped (batched) launches and the split two-component x stage.
 //
-// Part of libetdds: included, in order, by etdds.hip only (one translation
-// unit); every definition has internal linkage.
+// Part of libetdds: included, in order, by library.hpp (each translation
+// unit that includes it holds its own copy); internal linkage throughout.
 #pragma once
 
 namespace {

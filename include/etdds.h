@@ -19,7 +19,10 @@
  *    is double for ETD_FP64 and float for ETD_FP32 and ETD_BF16X6.
  *  - Device memory belongs to the caller: the field and one workspace buffer
  *    of etd_plan_workspace_bytes() bytes (256-byte aligned).  The library
- *    allocates no device memory.  A plan owns host memory only.
+ *    allocates no device memory.  A plan owns host memory only.  Every call
+ *    that takes a plan's workspace (advance, adjoint, compare, autotune,
+ *    graph capture) requires the one etd_plan_upload last filled for that
+ *    plan, else it returns ETD_EWORKSPACE before enqueueing anything.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Device work is enqueued asynchronously on it, in stream order.
  *  - Every call returns an etd_status.  Argument errors are detected on the
@@ -105,17 +108,29 @@ etd_status etd_plan_upload(const etd_plan* plan, void* workspace_dev, size_t byt
 
 /* Advance the field u_dev (device, layout above, updated in place) by nsteps
  * steps from time t0 (the time argument of f).  nsteps = 0 is a no-op.
- * Asynchronous on `stream`. */
+ * Asynchronous on `stream`.  ETD_EWORKSPACE unless workspace_dev is the
+ * workspace the plan was last uploaded to (etd_plan_upload records it; a
+ * later upload of another plan to the same memory takes it over). */
 etd_status etd_advance(const etd_plan* plan, void* u_dev, double t0, int nsteps,
                        void* workspace_dev, void* stream);
 
-/* Validation reductions over the interior (all components): out[0] =
+/* Validation reductions over the interior (all components), the ingredients
+ * of Sec. 5's error measures (the max-norm E(N) over grid points and
+ * components, and the relative 2-norm error out[0]/out[1]): out[0] =
  * ||a - b||_2, out[1] = ||b||_2, out[2] = max |a - b|, out[3] = number of
- * non-finite entries of a.  Accumulates in FP64 in a fixed order (repeatable).
- * Synchronises `stream` to return the result.  Returns ETD_ENONFINITE (with
- * out filled) when a holds NaN or Inf. */
+ * non-finite entries of a.  a and b are fields of the plan's layout and
+ * element type (device).  Entries where a is not finite are left out of
+ * out[0] and out[2] (and counted in out[3]); out[1] takes every entry of b.
+ * Accumulates in FP64 in a fixed order (repeatable).  Synchronises `stream`
+ * to return the result.  Returns ETD_ENONFINITE (with out filled) when a
+ * holds NaN or Inf; ETD_EWORKSPACE as etd_advance. */
 etd_status etd_compare(const etd_plan* plan, const void* a_dev, const void* b_dev, double out[4],
                        void* workspace_dev, void* stream);
+
+/* The problem the plan was created from (Sec. 1: dimension, grid, box,
+ * coefficients, time step, source and precision), copied to *out; lets a
+ * caller check a field's size and element type against the plan. */
+etd_status etd_plan_problem(const etd_plan* plan, etd_problem* out);
 
 /* Host copies of the plan's FP64 tables, for inspection and tests (no device
  * involvement).  which: 0 = eigenvalues lambda_j of A_d (component comp),

@@ -51,7 +51,8 @@ class etd_problem(ctypes.Structure):
 _lib = None
 
 EXPORTS = ("etd_plan_create", "etd_plan_workspace_bytes", "etd_plan_upload", "etd_advance", "etd_compare",
-           "etd_plan_table", "etd_timing_enable", "etd_timing_read", "etd_adjoint_workspace_bytes", "etd_adjoint",
+           "etd_plan_problem", "etd_plan_table", "etd_timing_enable", "etd_timing_read",
+           "etd_adjoint_workspace_bytes", "etd_adjoint",
            "etd_plan_tiles", "etd_plan_set_tiles", "etd_plan_autotune",
            "etd_batch_create", "etd_batch_workspace_bytes", "etd_batch_upload", "etd_batch_advance",
            "etd_batch_autotune", "etd_batch_tiles", "etd_batch_groups", "etd_batch_destroy",
@@ -75,6 +76,7 @@ def lib():
             "etd_plan_upload": [vp, vp, sz, vp],
             "etd_advance": [vp, vp, d, ip, vp, vp],
             "etd_compare": [vp, vp, vp, dp, vp, vp],
+            "etd_plan_problem": [vp, ctypes.POINTER(etd_problem)],
             "etd_plan_table": [vp, ip, ip, ip, dp, sz],
             "etd_timing_enable": [vp, ip],
             "etd_timing_read": [vp, dp, ctypes.POINTER(ctypes.c_longlong)],
@@ -148,6 +150,41 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _field_spec(plan):
+    """(element count, torch dtype) of a field of the plan's problem."""
+    import torch
+    pr = etd_plan_problem(plan)
+    n = pr.ncomp
+    for d in range(pr.dim):
+        n *= pr.n[d]
+    return n, (torch.float64 if pr.precision == ETD_FP64 else torch.float32)
+
+
+def _check_device(t, what):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor (got {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
+def _check_field(plan, t, what="field", workspace=None):
+    """Raise before any library call unless t is a contiguous device tensor of
+    the plan's element type and field size (on the workspace's device)."""
+    _check_device(t, what)
+    n, dt = _field_spec(plan)
+    if t.dtype != dt:
+        raise ValueError(f"{what} has dtype {t.dtype}; the plan's precision needs {dt}")
+    if t.numel() != n:
+        raise ValueError(f"{what} has {t.numel()} elements; the plan's field has {n}")
+    if workspace is not None:
+        _check_device(workspace, "workspace")
+        if workspace.device != t.device:
+            raise ValueError(f"{what} is on {t.device} but the workspace on {workspace.device}")
+
+
 # --------------------------------------------------------------------------
 # entry points (same names as include/etdds.h)
 # --------------------------------------------------------------------------
@@ -171,17 +208,24 @@ def etd_plan_upload(plan, workspace, stream=None):
 
 
 def etd_advance(plan, u, t0: float, nsteps: int, workspace, stream=None):
-    if not u.is_contiguous():
-        raise ValueError("field must be contiguous")
+    _check_field(plan, u, "field", workspace)
     _check(lib().etd_advance(plan, _ptr(u), float(t0), int(nsteps), _ptr(workspace), _stream(stream)))
 
 
 def etd_compare(plan, a, b, workspace, stream=None, allow_nonfinite: bool = False):
+    _check_field(plan, a, "a", workspace)
+    _check_field(plan, b, "b", workspace)
     out = (ctypes.c_double * 4)()
     st = lib().etd_compare(plan, _ptr(a), _ptr(b), out, _ptr(workspace), _stream(stream))
     if not (allow_nonfinite and st == ETD_ENONFINITE):
         _check(st)
     return tuple(out)
+
+
+def etd_plan_problem(plan) -> etd_problem:
+    out = etd_problem()
+    _check(lib().etd_plan_problem(plan, ctypes.byref(out)))
+    return out
 
 
 def etd_plan_table(plan, which: int, d: int, comp: int, count: int) -> np.ndarray:
@@ -212,6 +256,10 @@ def etd_adjoint_workspace_bytes(plan, nsteps: int) -> int:
 def etd_adjoint(plan, u0, t0: float, nsteps: int, ubar_final, ubar0, workspace, adjoint_workspace, ncomp: int,
                 stream=None):
     """Returns [dL/dkappa_0, ..., dL/dkappa_{ncomp-1}, dL/dq]; writes dL/du0 into ubar0."""
+    _check_field(plan, u0, "u0", workspace)
+    _check_field(plan, ubar_final, "ubar_final", workspace)
+    _check_field(plan, ubar0, "ubar0", workspace)
+    _check_device(adjoint_workspace, "adjoint workspace")
     grad = (ctypes.c_double * (ncomp + 1))()
     nbytes = adjoint_workspace.numel() * adjoint_workspace.element_size()
     _check(lib().etd_adjoint(plan, _ptr(u0), float(t0), int(nsteps), _ptr(ubar_final), _ptr(ubar0), grad,
@@ -257,9 +305,8 @@ def etd_batch_upload(batch, workspace, stream=None):
 
 
 def _ptr_array(fields):
-    for f in fields:
-        if not f.is_contiguous():
-            raise ValueError("fields must be contiguous")
+    for i, f in enumerate(fields):
+        _check_device(f, f"field {i}")
     return (ctypes.c_void_p * len(fields))(*[f.data_ptr() for f in fields])
 
 
@@ -289,6 +336,7 @@ def etd_batch_destroy(batch):
 
 
 def etd_graph_capture(plan, u, t0: float, nsteps: int, workspace, stream) -> ctypes.c_void_p:
+    _check_field(plan, u, "field", workspace)
     h = ctypes.c_void_p()
     _check(lib().etd_graph_capture(plan, _ptr(u), float(t0), int(nsteps), _ptr(workspace), _stream(stream),
                                    ctypes.byref(h)))
@@ -362,7 +410,7 @@ class Stepper:
         raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-raw.data_ptr()) % 256
         aws = raw[off:off + nbytes]
-        ubar0 = torch.empty_like(u0)
+        ubar0 = torch.empty(tuple(self.problem.shape), dtype=self.dtype, device=self.device)
         grad = etd_adjoint(self.plan, u0.contiguous(), t0, nsteps, ubar_final.contiguous(), ubar0, self.workspace,
                            aws, self.problem.ncomp, self.stream)
         return ubar0, grad
@@ -437,7 +485,19 @@ class Batch:
         return [torch.as_tensor(np.ascontiguousarray(u), dtype=self.dtype).reshape(p.shape).to(self.device)
                 .contiguous() for p, u in zip(self.problems, u0s)]
 
+    def check_fields(self, fields):
+        """Raise unless fields[i] is a contiguous device tensor of instance
+        i's element type and size, on the batch's device."""
+        if len(fields) != len(self.problems):
+            raise ValueError(f"{len(fields)} fields for {len(self.problems)} instances")
+        for i, (p, f) in enumerate(zip(self.problems, fields)):
+            _check_device(f, f"field {i}")
+            if f.dtype != self.dtype or f.numel() != int(np.prod(p.shape)) or f.device != self.workspace.device:
+                raise ValueError(f"field {i}: {f.dtype} x {f.numel()} on {f.device}; instance {i} needs "
+                                 f"{self.dtype} x {int(np.prod(p.shape))} on {self.workspace.device}")
+
     def advance(self, fields, nsteps: int, t0: float = 0.0):
+        self.check_fields(fields)
         etd_batch_advance(self.batch, fields, t0, nsteps, self.workspace, self.stream)
         return fields
 
@@ -451,6 +511,7 @@ class Batch:
         return etd_batch_groups(self.batch)
 
     def capture(self, fields, nsteps: int, stream, t0: float = 0.0) -> Graph:
+        self.check_fields(fields)
         h = etd_batch_graph_capture(self.batch, fields, t0, nsteps, self.workspace, stream)
         return Graph(h, (self, list(fields)))
 
@@ -481,18 +542,22 @@ def _autograd():
             p = problem.replace(kappa=tuple(float(k) for k in kappa.detach().cpu().reshape(-1)),
                                 q=float(q.detach().cpu()))
             st = Stepper(p, device=u0.device)
-            u = u0.detach().clone().contiguous()
+            # the field in the plan's element type (an FP64 u0 for an FP32
+            # problem is rounded once here; results come back as u0's dtype)
+            u = u0.detach().to(st.dtype).clone().contiguous()
+            ctx.save_for_backward(u.clone())
             st.advance(u, nsteps, t0)
-            ctx.save_for_backward(u0.detach().clone())
             ctx.stepper, ctx.nsteps, ctx.t0 = st, nsteps, t0
             ctx.kshape, ctx.kdev, ctx.qdev = kappa.shape, kappa.device, q.device
-            return u
+            ctx.udtype = u0.dtype
+            return u.to(u0.dtype)
 
         @staticmethod
         def backward(ctx, ubar):
             (u0,) = ctx.saved_tensors
             st = ctx.stepper
-            ubar0, grad = st.adjoint(u0, ubar.contiguous(), ctx.nsteps, ctx.t0)
+            ubar0, grad = st.adjoint(u0, ubar.to(st.dtype).contiguous(), ctx.nsteps, ctx.t0)
+            ubar0 = ubar0.to(ctx.udtype)
             nc = st.problem.ncomp
             gk = torch.tensor(grad[:nc], dtype=torch.float64, device=ctx.kdev).reshape(ctx.kshape)
             gq = torch.tensor(grad[nc], dtype=torch.float64, device=ctx.qdev)

@@ -33,6 +33,7 @@ thread_local std::string g_err;
 struct etd_plan {
     Plan p;
     mutable StageTimer timer;
+    unsigned long long serial = 0;   // unique per plan (workspace registry)
 };
 
 struct etd_batch {
@@ -47,6 +48,29 @@ struct etd_graph {
 };
 
 namespace {
+
+// The plan whose tables each workspace holds: etd_plan_upload records the
+// workspace address with the plan's serial number, and every call that takes
+// a plan workspace checks it, so a workspace that was never uploaded, or was
+// last uploaded for another plan, is refused instead of yielding garbage
+// tables (or, undersized, stage writes beyond its end).
+std::mutex g_ws_mutex;
+std::unordered_map<const void*, unsigned long long> g_ws_owner;
+std::atomic<unsigned long long> g_plan_serial{0};
+
+etd_status check_uploaded(const etd_plan* plan, const void* ws) {
+    std::lock_guard<std::mutex> lk(g_ws_mutex);
+    const auto it = g_ws_owner.find(ws);
+    if (it == g_ws_owner.end() || it->second != plan->serial)
+        return fail(ETD_EWORKSPACE, "workspace was not uploaded for this plan (etd_plan_upload)");
+    return ETD_OK;
+}
+
+// check_ws (pointer and alignment), then the upload record
+etd_status check_plan_ws(const etd_plan* plan, const void* ws) {
+    const etd_status st = check_ws(plan->p, ws);
+    return st != ETD_OK ? st : check_uploaded(plan, ws);
+}
 
 const PrecisionOps& ops_for(int precision) {
     switch (precision) {
@@ -92,6 +116,7 @@ etd_status etd_plan_create(const etd_problem* prob, etd_plan** out) {
         delete p;
         return fail(st, err);
     }
+    p->serial = ++g_plan_serial;
     *out = p;
     return ETD_OK;
 }
@@ -116,6 +141,8 @@ etd_status etd_plan_upload(const etd_plan* plan, void* ws, size_t bytes, void* s
             "workspace clear");
     // The host image must outlive the asynchronous copy.
     HIP_TRY(hipStreamSynchronize(s), "table upload sync");
+    std::lock_guard<std::mutex> lk(g_ws_mutex);
+    g_ws_owner[ws] = plan->serial;
     return ETD_OK;
 }
 
@@ -127,6 +154,8 @@ etd_status etd_advance(const etd_plan* plan, void* u, double t0, int nsteps, voi
     etd_status st = check_ws(plan->p, ws);
     if (st != ETD_OK) return st;
     if (nsteps == 0) return ETD_OK;
+    st = check_uploaded(plan, ws);
+    if (st != ETD_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(ws);
     return ops_for(plan->p.prob.precision).advance(plan->p, plan->timer, u, t0, nsteps, w, s);
@@ -146,7 +175,7 @@ etd_status etd_adjoint(const etd_plan* plan, const void* u0, double t0, int nste
     if (!plan || !u0 || !ubar_final || !ubar0 || !grad) return fail(ETD_EINVAL, "NULL argument");
     if (nsteps < 1) return fail(ETD_EINVAL, "nsteps must be >= 1");
     if (!std::isfinite(t0)) return fail(ETD_EINVAL, "t0 must be finite");
-    etd_status st = check_ws(plan->p, ws);
+    etd_status st = check_plan_ws(plan, ws);
     if (st != ETD_OK) return st;
     st = adjoint_supported(plan->p);
     if (st != ETD_OK) return st;
@@ -163,7 +192,7 @@ etd_status etd_adjoint(const etd_plan* plan, const void* u0, double t0, int nste
 
 etd_status etd_plan_autotune(etd_plan* plan, void* ws, void* stream) {
     if (!plan) return fail(ETD_EINVAL, "NULL plan");
-    etd_status st = check_ws(plan->p, ws);
+    etd_status st = check_plan_ws(plan, ws);
     if (st != ETD_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(ws);
@@ -364,7 +393,7 @@ etd_status etd_graph_capture(const etd_plan* plan, void* u, double t0, int nstep
     if (!stream) return fail(ETD_EINVAL, "graph capture needs a stream other than the default stream");
     if (nsteps < 1) return fail(ETD_EINVAL, "nsteps must be >= 1");
     if (!std::isfinite(t0)) return fail(ETD_EINVAL, "t0 must be finite");
-    etd_status st = check_ws(plan->p, ws);
+    etd_status st = check_plan_ws(plan, ws);
     if (st != ETD_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bool timing = plan->timer.on;
@@ -444,7 +473,7 @@ etd_status etd_graph_destroy(etd_graph* graph) {
 
 etd_status etd_compare(const etd_plan* plan, const void* a, const void* b, double out[4], void* ws, void* stream) {
     if (!plan || !a || !b || !out) return fail(ETD_EINVAL, "NULL argument");
-    etd_status st = check_ws(plan->p, ws);
+    etd_status st = check_plan_ws(plan, ws);
     if (st != ETD_OK) return st;
     const Plan& pl = plan->p;
     const long n = long(pl.nc) * pl.n[0] * pl.n[1] * pl.n[2];
@@ -462,6 +491,12 @@ etd_status etd_compare(const etd_plan* plan, const void* a, const void* b, doubl
     HIP_TRY(hipMemcpyAsync(out, part + kRedBlocks * 4, 4 * sizeof(double), hipMemcpyDeviceToHost, s), "compare copy");
     HIP_TRY(hipStreamSynchronize(s), "compare sync");
     if (out[3] > 0) return fail(ETD_ENONFINITE, "field holds non-finite values");
+    return ETD_OK;
+}
+
+etd_status etd_plan_problem(const etd_plan* plan, etd_problem* out) {
+    if (!plan || !out) return fail(ETD_EINVAL, "NULL argument");
+    *out = plan->p.prob;
     return ETD_OK;
 }
 
@@ -508,8 +543,12 @@ etd_status etd_timing_read(etd_plan* plan, double ms[3], long long counts[3]) {
 }
 
 etd_status etd_plan_destroy(etd_plan* plan) {
-    if (plan)
+    if (plan) {
         for (hipEvent_t e : plan->timer.pool) (void)hipEventDestroy(e);
+        std::lock_guard<std::mutex> lk(g_ws_mutex);
+        for (auto it = g_ws_owner.begin(); it != g_ws_owner.end();)
+            it = it->second == plan->serial ? g_ws_owner.erase(it) : std::next(it);
+    }
     delete plan;
     return ETD_OK;
 }

@@ -47,7 +47,9 @@ __global__ void unpack_field(const T* __restrict__ src, T* __restrict__ dst, Dim
 constexpr int kRedBlocks = 1024;
 constexpr int kRedThreads = 256;
 
-// Per-block partial sums in a fixed order: [sum (a-b)^2, sum b^2, max|a-b|, #nonfinite(a)].
+// Per-block partial sums in a fixed order: [sum (a-b)^2, sum b^2, max|a-b|,
+// #nonfinite(a)]; the difference terms skip the entries where a is not
+// finite, sum b^2 takes every entry.
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void compare_partial(const T* __restrict__ a, const T* __restrict__ b,
                                                                long n, double* __restrict__ part) {
@@ -55,13 +57,13 @@ __global__ __launch_bounds__(kRedThreads) void compare_partial(const T* __restri
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     for (long i = blockIdx.x * long(kRedThreads) + threadIdx.x; i < n; i += long(gridDim.x) * kRedThreads) {
         const double av = double(a[i]), bv = double(b[i]);
+        s1 += bv * bv;   // ||b|| over every entry, whatever a holds
         if (!isfinite(av)) {
             s3 += 1.0;
             continue;
         }
         const double df = av - bv;
         s0 += df * df;
-        s1 += bv * bv;
         s2 = fmax(s2, fabs(df));
     }
     sh[0][threadIdx.x] = s0;

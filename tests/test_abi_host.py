@@ -174,6 +174,18 @@ def test_host_side_argument_errors_touch_nothing(etd):
         assert L.etd_advance(plan, fake_u, 0.0, 0, ctypes.c_void_p(0x10000), None) == etd.ETD_OK
         assert L.etd_plan_upload(plan, ctypes.c_void_p(0x10000), nbytes - 1, None) == etd.ETD_EWORKSPACE
         assert "smaller" in etd.etd_last_error()
+        # an aligned workspace that etd_plan_upload never filled for this plan
+        ws = ctypes.c_void_p(0x10000)
+        assert L.etd_advance(plan, fake_u, 0.0, 1, ws, None) == etd.ETD_EWORKSPACE
+        assert "not uploaded" in etd.etd_last_error()
+        out = (ctypes.c_double * 4)()
+        assert L.etd_compare(plan, fake_u, fake_u, out, ws, None) == etd.ETD_EWORKSPACE
+        assert L.etd_plan_autotune(plan, ws, None) == etd.ETD_EWORKSPACE
+        g = (ctypes.c_double * 2)()
+        assert L.etd_adjoint(plan, fake_u, 0.0, 2, fake_u, fake_u, g, ws, ws, 1 << 30, None) == etd.ETD_EWORKSPACE
+        h = ctypes.c_void_p()
+        assert L.etd_graph_capture(plan, fake_u, 0.0, 1, ws, ctypes.c_void_p(0x20), ctypes.byref(h)) == \
+            etd.ETD_EWORKSPACE
         assert etd.etd_status_string(etd.ETD_EWORKSPACE) == "bad workspace"
     finally:
         etd.etd_plan_destroy(plan)
@@ -397,3 +409,35 @@ def test_batch_holds_one_p_per_extent(etd):
         assert total % 256 == 0
         # k regions, the last k - 1 without their P tables, plus the descriptor table (< 64 KiB here)
         assert k * single - (k - 1) * p_bytes <= total < k * single - (k - 1) * p_bytes + 65536
+
+
+def test_plan_problem_round_trip(etd):
+    """etd_plan_problem returns the problem the plan was built from."""
+    p = W.Problem(dim=3, n=(20, 14, 17), kappa=(0.01, 0.003), q=0.2, tau=0.05, reaction="fhn_classic",
+                  rxn_param=(0.7, 1.2), precision="fp32", pade=4)
+    plan = etd.etd_plan_create(p)
+    try:
+        got = etd.etd_plan_problem(plan)
+        ref = etd.problem_struct(p)
+        assert bytes(got) == bytes(ref)
+    finally:
+        etd.etd_plan_destroy(plan)
+
+
+def test_binding_rejects_host_and_mismatched_tensors(etd):
+    """The binding checks every tensor before any library call: host tensors,
+    a wrong element type or a wrong size raise ValueError (no device needed,
+    so no fake address ever reaches a kernel)."""
+    import torch
+    p = W.Problem(dim=2, n=(31, 33), kappa=(0.1,), tau=0.01, reaction="fisher", precision="fp32")
+    plan = etd.etd_plan_create(p)
+    try:
+        host = torch.zeros(p.shape, dtype=torch.float32)
+        with pytest.raises(ValueError, match="device tensor"):
+            etd.etd_advance(plan, host, 0.0, 1, host)
+        with pytest.raises(ValueError, match="device tensor"):
+            etd.etd_compare(plan, host, host, host)
+        n, dt = etd._field_spec(plan)
+        assert n == 31 * 33 and dt == torch.float32
+    finally:
+        etd.etd_plan_destroy(plan)

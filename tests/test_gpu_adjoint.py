@@ -170,3 +170,29 @@ def test_adjoint_is_repeatable(etd):
     b0, gb = st.adjoint(u0, ub, 10)
     st.close()
     assert torch.equal(a0, b0) and ga == gb
+
+
+def test_autograd_fp32_problem_with_float64_u0(etd):
+    """An FP32 problem given a float64 u0 (what the workload generators
+    return): the forward rounds u0 once to FP32, and the gradients equal those
+    of Stepper.adjoint on that rounded u0, returned as float64."""
+    import torch
+    p = W.Problem(dim=2, n=(30, 33), kappa=(0.01, 0.002), q=0.1, tau=0.05, reaction="fhn_cubic",
+                  precision="fp32")
+    u0 = torch.tensor(W.u0_fhn_patch(p, 5, patch=0.4), device="cuda", dtype=torch.float64, requires_grad=True)
+    kappa = torch.tensor(p.kappa, dtype=torch.float64, requires_grad=True)
+    q = torch.tensor(p.q, dtype=torch.float64, requires_grad=True)
+    uN = etd.advance_autograd(u0, kappa, q, p, 9)
+    assert uN.dtype == torch.float64
+    target = 0.9 * u0.detach()
+    loss = 0.5 * ((uN - target) ** 2).sum()
+    loss.backward()
+    assert u0.grad.dtype == torch.float64
+    st = etd.Stepper(p)
+    u32 = u0.detach().float().contiguous()
+    ref = st.advance(u32.clone(), 9)
+    assert torch.equal(uN.float(), ref)
+    ubar0, grad = st.adjoint(u32, (uN - target).detach().float().contiguous(), 9)
+    st.close()
+    assert torch.equal(u0.grad, ubar0.double())
+    assert kappa.grad.tolist() == grad[:2] and float(q.grad) == grad[2]

@@ -380,6 +380,10 @@ def test_compare_reduction(etd):
     assert ei.value.status == etd.ETD_ENONFINITE
     out = st.compare(st.field(a), st.field(b), allow_nonfinite=True)
     assert out[3] == 2
+    # ||b|| takes every entry of b; the difference terms skip a's non-finite ones
+    assert math.isclose(out[1], np.linalg.norm(b.ravel()), rel_tol=1e-12)
+    fin = np.isfinite(a)
+    assert math.isclose(out[0], np.linalg.norm((a - b)[fin]), rel_tol=1e-12)
     st.close()
 
 

@@ -127,6 +127,25 @@ etd_status etd_advance(const etd_plan* plan, void* u_dev, double t0, int nsteps,
 etd_status etd_compare(const etd_plan* plan, const void* a_dev, const void* b_dev, double out[4],
                        void* workspace_dev, void* stream);
 
+/* etd_compare for callers that cannot allocate device memory or hand over a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Computes the same four values as etd_compare, with
+ * the same kernels in the same order (bit-identical results), but:
+ *  - it needs no workspace and no etd_plan_upload: the per-workgroup partial
+ *    sums go to a fixed array inside the library's device code (1024 x 4
+ *    doubles, 32 KB per GPU, held until the process ends).  The reduction
+ *    strides over the field, so fields of any size fit and no size is refused;
+ *  - out_dev is a device array of 4 doubles that receives out[0..3]; nothing
+ *    is copied to the host and `stream` is not synchronised, so the call can
+ *    be captured into a graph; non-finite entries are reported in out_dev[3]
+ *    only (the return value is ETD_OK once the work is enqueued).
+ * Every call on one GPU uses that GPU's one array and overwrites all of it
+ * before reading it: calls that overlap on one GPU (other streams or host
+ * threads) race and must be serialised by the caller.  ETD_EINVAL on NULL
+ * arguments; ETD_EHIP on a launch error. */
+etd_status etd_compare_noalloc(const etd_plan* plan, const void* a_dev, const void* b_dev, double* out_dev,
+                               void* stream);
+
 /* The problem the plan was created from (Sec. 1: dimension, grid, box,
  * coefficients, time step, source and precision), copied to *out; lets a
  * caller check a field's size and element type against the plan. */

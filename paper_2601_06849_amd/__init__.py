@@ -51,6 +51,7 @@ class etd_problem(ctypes.Structure):
 _lib = None
 
 EXPORTS = ("etd_plan_create", "etd_plan_workspace_bytes", "etd_plan_upload", "etd_advance", "etd_compare",
+           "etd_compare_noalloc",
            "etd_plan_problem", "etd_plan_table", "etd_timing_enable", "etd_timing_read",
            "etd_adjoint_workspace_bytes", "etd_adjoint",
            "etd_plan_tiles", "etd_plan_set_tiles", "etd_plan_autotune",
@@ -76,6 +77,7 @@ def lib():
             "etd_plan_upload": [vp, vp, sz, vp],
             "etd_advance": [vp, vp, d, ip, vp, vp],
             "etd_compare": [vp, vp, vp, dp, vp, vp],
+            "etd_compare_noalloc": [vp, vp, vp, vp, vp],
             "etd_plan_problem": [vp, ctypes.POINTER(etd_problem)],
             "etd_plan_table": [vp, ip, ip, ip, dp, sz],
             "etd_timing_enable": [vp, ip],
@@ -220,6 +222,20 @@ def etd_compare(plan, a, b, workspace, stream=None, allow_nonfinite: bool = Fals
     if not (allow_nonfinite and st == ETD_ENONFINITE):
         _check(st)
     return tuple(out)
+
+
+def etd_compare_noalloc(plan, a, b, out, stream=None):
+    """etd_compare without a workspace: the four results go to the device
+    tensor `out` (4 float64), asynchronously on the stream."""
+    import torch
+    _check_field(plan, a, "a")
+    _check_field(plan, b, "b")
+    _check_device(out, "out")
+    if out.dtype != torch.float64 or out.numel() < 4:
+        raise ValueError("out must be a device float64 tensor of at least 4 elements")
+    if a.device != b.device or out.device != a.device:
+        raise ValueError("a, b and out must be on one device")
+    _check(lib().etd_compare_noalloc(plan, _ptr(a), _ptr(b), _ptr(out), _stream(stream)))
 
 
 def etd_plan_problem(plan) -> etd_problem:

@@ -97,6 +97,51 @@ etd_status batch_check(const Batch& B, void* const* u, int nsteps, const void* w
     return ETD_OK;
 }
 
+// The validation reductions of etd_compare: per-block partials into part
+// (kRedBlocks x 4 doubles), then the four results into res (device).
+etd_status compare_enqueue(const Plan& pl, const void* a, const void* b, double* part, double* res, hipStream_t s) {
+    const long n = long(pl.nc) * pl.n[0] * pl.n[1] * pl.n[2];
+    if (pl.prob.precision == ETD_FP64)
+        hipLaunchKernelGGL(compare_partial<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, s,
+                           static_cast<const double*>(a), static_cast<const double*>(b), n, part);
+    else
+        hipLaunchKernelGGL(compare_partial<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, s,
+                           static_cast<const float*>(a), static_cast<const float*>(b), n, part);
+    HIP_TRY(hipGetLastError(), "compare launch");
+    hipLaunchKernelGGL(compare_final, dim3(1), dim3(kRedThreads), 0, s, part, kRedBlocks, res);
+    HIP_TRY(hipGetLastError(), "compare final launch");
+    return ETD_OK;
+}
+
+// Partial sums of etd_compare_noalloc: a fixed device array (one copy per
+// GPU, held until the process ends).  The grid-stride reduction writes
+// exactly kRedBlocks x 4 partials whatever the field size, and every call
+// overwrites all of them before reading, so nothing needs clearing; calls
+// that overlap on one GPU share the array and race.
+constexpr int kScratchDoubles = kRedBlocks * 4;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// Device address of `scratch` per device ordinal, looked up once per device
+// with that device current (the array's host-side name is not a device
+// address).
+std::mutex g_scratch_mutex;
+std::vector<double*> g_scratch_ptr;
+
+etd_status scratch_on_current_device(double** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "current device");
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (dev >= int(g_scratch_ptr.size())) g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch symbol address");
+        if (!p) return fail(ETD_EHIP, "scratch symbol address: NULL");
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return ETD_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -475,23 +520,22 @@ etd_status etd_compare(const etd_plan* plan, const void* a, const void* b, doubl
     if (!plan || !a || !b || !out) return fail(ETD_EINVAL, "NULL argument");
     etd_status st = check_plan_ws(plan, ws);
     if (st != ETD_OK) return st;
-    const Plan& pl = plan->p;
-    const long n = long(pl.nc) * pl.n[0] * pl.n[1] * pl.n[2];
     hipStream_t s = static_cast<hipStream_t>(stream);
-    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + pl.lay.reduce);
-    if (pl.prob.precision == ETD_FP64)
-        hipLaunchKernelGGL(compare_partial<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, s,
-                           static_cast<const double*>(a), static_cast<const double*>(b), n, part);
-    else
-        hipLaunchKernelGGL(compare_partial<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, s,
-                           static_cast<const float*>(a), static_cast<const float*>(b), n, part);
-    HIP_TRY(hipGetLastError(), "compare launch");
-    hipLaunchKernelGGL(compare_final, dim3(1), dim3(kRedThreads), 0, s, part, kRedBlocks);
-    HIP_TRY(hipGetLastError(), "compare final launch");
+    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + plan->p.lay.reduce);
+    st = compare_enqueue(plan->p, a, b, part, part + kRedBlocks * 4, s);
+    if (st != ETD_OK) return st;
     HIP_TRY(hipMemcpyAsync(out, part + kRedBlocks * 4, 4 * sizeof(double), hipMemcpyDeviceToHost, s), "compare copy");
     HIP_TRY(hipStreamSynchronize(s), "compare sync");
     if (out[3] > 0) return fail(ETD_ENONFINITE, "field holds non-finite values");
     return ETD_OK;
+}
+
+etd_status etd_compare_noalloc(const etd_plan* plan, const void* a, const void* b, double* out_dev, void* stream) {
+    if (!plan || !a || !b || !out_dev) return fail(ETD_EINVAL, "NULL argument");
+    double* part = nullptr;
+    etd_status st = scratch_on_current_device(&part);
+    if (st != ETD_OK) return st;
+    return compare_enqueue(plan->p, a, b, part, out_dev, static_cast<hipStream_t>(stream));
 }
 
 etd_status etd_plan_problem(const etd_plan* plan, etd_problem* out) {

@@ -83,7 +83,10 @@ __global__ __launch_bounds__(kRedThreads) void compare_partial(const T* __restri
     if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(kRedThreads) void compare_final(double* __restrict__ part, int nblocks) {
+// Reduce the nblocks per-block partials (fixed order) into res[0..3] =
+// [||a-b||_2, ||b||_2, max|a-b|, #nonfinite(a)].
+__global__ __launch_bounds__(kRedThreads) void compare_final(const double* __restrict__ part, int nblocks,
+                                                             double* __restrict__ res) {
     __shared__ double sh[4][kRedThreads];
     double s[4] = {0, 0, 0, 0};
     for (int i = threadIdx.x; i < nblocks; i += kRedThreads) {
@@ -104,10 +107,10 @@ __global__ __launch_bounds__(kRedThreads) void compare_final(double* __restrict_
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        part[nblocks * 4 + 0] = sqrt(sh[0][0]);
-        part[nblocks * 4 + 1] = sqrt(sh[1][0]);
-        part[nblocks * 4 + 2] = sh[2][0];
-        part[nblocks * 4 + 3] = sh[3][0];
+        res[0] = sqrt(sh[0][0]);
+        res[1] = sqrt(sh[1][0]);
+        res[2] = sh[2][0];
+        res[3] = sh[3][0];
     }
 }
 

@@ -16,7 +16,8 @@
  *  - n[d] counts interior points; h_d = (hi[d]-lo[d])/(n[d]+1) (Sec. 2.1).
  *  - A field is a contiguous device array ncomp x nz x ny x nx, x fastest
  *    (the vectorisation order of Sec. 2.1), nz = 1 in 2-D.  Its element type
- *    is double for ETD_FP64 and float for ETD_FP32 and ETD_BF16X6.
+ *    is double for ETD_FP64, ETD_FP64_FP32 and ETD_FP64_BF16X6 and float for
+ *    ETD_FP32 and ETD_BF16X6.
  *  - Device memory belongs to the caller: the field and one workspace buffer
  *    of etd_plan_workspace_bytes() bytes (256-byte aligned).  The library
  *    allocates no device memory.  A plan owns host memory only.  Every call
@@ -51,8 +52,14 @@ typedef enum {
 typedef enum {
     ETD_FP64 = 0,   /* FP64 state, FP64 MFMA mode products */
     ETD_FP32 = 1,   /* FP32 state, FP32 MFMA mode products */
-    ETD_BF16X6 = 2  /* FP32 state; mode products as six BF16 MFMA terms
+    ETD_BF16X6 = 2, /* FP32 state; mode products as six BF16 MFMA terms
                        (hi/mid/lo splits of both operands), FP32 accumulation */
+    ETD_FP64_FP32 = 3,   /* FP64 state, diagonals and epilogues; FP32 MFMA mode
+                            products (P held in FP32, the other operand rounded
+                            to FP32 as it is read), FP32 accumulation */
+    ETD_FP64_BF16X6 = 4  /* FP64 state, diagonals and epilogues; split-BF16
+                            mode products as in ETD_BF16X6 (the other operand
+                            rounded to FP32, then split) */
 } etd_precision;
 
 typedef enum {

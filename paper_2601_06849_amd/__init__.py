@@ -18,11 +18,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libetdds.so")
 
 ETD_OK, ETD_EINVAL, ETD_EUNSUPPORTED, ETD_EWORKSPACE, ETD_EHIP, ETD_ENONFINITE = 0, -1, -2, -3, -4, -5
-ETD_FP64, ETD_FP32, ETD_BF16X6 = 0, 1, 2
+ETD_FP64, ETD_FP32, ETD_BF16X6, ETD_FP64_FP32, ETD_FP64_BF16X6 = 0, 1, 2, 3, 4
 
 RXN = {"none": 0, "linear": 1, "fisher": 2, "allen_cahn": 3, "ac_mms": 4, "saturating": 5,
        "fhn_cubic": 6, "fhn_classic": 7}
-PRECISION = {"fp64": ETD_FP64, "fp32": ETD_FP32, "bf16x6": ETD_BF16X6}
+PRECISION = {"fp64": ETD_FP64, "fp32": ETD_FP32, "bf16x6": ETD_BF16X6, "fp64_fp32": ETD_FP64_FP32,
+             "fp64_bf16x6": ETD_FP64_BF16X6}
+# precisions whose state (fields) is FP64
+FP64_STATE = ("fp64", "fp64_fp32", "fp64_bf16x6")
 
 
 class EtdError(RuntimeError):
@@ -159,7 +162,7 @@ def _field_spec(plan):
     n = pr.ncomp
     for d in range(pr.dim):
         n *= pr.n[d]
-    return n, (torch.float64 if pr.precision == ETD_FP64 else torch.float32)
+    return n, (torch.float64 if pr.precision in (ETD_FP64, ETD_FP64_FP32, ETD_FP64_BF16X6) else torch.float32)
 
 
 def _check_device(t, what):
@@ -397,7 +400,7 @@ class Stepper:
         import torch
         self.problem = problem
         self.device = torch.device(device)
-        self.dtype = torch.float64 if problem.precision == "fp64" else torch.float32
+        self.dtype = torch.float64 if problem.precision in FP64_STATE else torch.float32
         self.plan = etd_plan_create(problem)
         nbytes = etd_plan_workspace_bytes(self.plan)
         # over-allocate so the workspace can start on a 256-byte boundary
@@ -487,7 +490,7 @@ class Batch:
         import torch
         self.problems = list(problems)
         self.device = torch.device(device)
-        self.dtype = torch.float64 if self.problems[0].precision == "fp64" else torch.float32
+        self.dtype = torch.float64 if self.problems[0].precision in FP64_STATE else torch.float32
         self.batch = etd_batch_create(self.problems)
         nbytes = etd_batch_workspace_bytes(self.batch)
         self._raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)

@@ -79,6 +79,8 @@ template <typename M, int NC, int RB, int MAXT>
 __global__ __launch_bounds__(MAXT) void x_adjoint(XAdjArgs a) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
+    typedef typename M::acc AT;                 // accumulator type of the products
+    typedef typename Vec4<AT>::type A4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
     constexpr int UB = 0, WW = NC, VV = 2 * NC, FW = 3 * NC, S1 = 4 * NC, SW = 5 * NC, SV = 6 * NC, GS = 7 * NC;
@@ -121,8 +123,8 @@ __global__ __launch_bounds__(MAXT) void x_adjoint(XAdjArgs a) {
     // ---- S1 = P ubar, Sw = P w, Sv = P v ----
     T4 ub[RB][NC];
     {
-        T4 acc[RB][3 * NC];
-        zero<T, RB, 3 * NC>(acc);
+        A4 acc[RB][3 * NC];
+        zero<AT, RB, 3 * NC>(acc);
         gemm<M, RB, 3 * NC>(P, NP, rb0, li, lg, acc, bfrag_from(0));
 #pragma unroll
         for (int r = 0; r < RB; ++r)
@@ -147,8 +149,8 @@ __global__ __launch_bounds__(MAXT) void x_adjoint(XAdjArgs a) {
     for (int k = 0; k <= NC; ++k) gacc[k] = 0.0;
     T4 g[RB][NC], wb[RB][NC];
     {
-        T4 acc[RB][NC];
-        zero<T, RB, NC>(acc);
+        A4 acc[RB][NC];
+        zero<AT, RB, NC>(acc);
         gemm<M, RB, NC>(P, NP, rb0, li, lg, acc, bfrag_from(GS));
 #pragma unroll
         for (int r = 0; r < RB; ++r)
@@ -182,8 +184,8 @@ __global__ __launch_bounds__(MAXT) void x_adjoint(XAdjArgs a) {
 
     // ---- Sd = P d, S2 = P Wbar; gradient terms; scaled coefficients of S2 ----
     {
-        T4 acc[RB][2 * NC];
-        zero<T, RB, 2 * NC>(acc);
+        A4 acc[RB][2 * NC];
+        zero<AT, RB, 2 * NC>(acc);
         gemm<M, RB, 2 * NC>(P, NP, rb0, li, lg, acc, bfrag_from(UB));
 #pragma unroll
         for (int r = 0; r < RB; ++r)
@@ -210,8 +212,8 @@ __global__ __launch_bounds__(MAXT) void x_adjoint(XAdjArgs a) {
 
     // ---- wbar = Wbar + P ((q1 - 1) S2); vbar = -g + tau Wbar + P (tau (q2 - 1) S2) ----
     {
-        T4 acc[RB][2 * NC];
-        zero<T, RB, 2 * NC>(acc);
+        A4 acc[RB][2 * NC];
+        zero<AT, RB, 2 * NC>(acc);
         gemm<M, RB, 2 * NC>(P, NP, rb0, li, lg, acc, bfrag_from(VV));
         T* __restrict__ ow = static_cast<T*>(a.wbar);
         T* __restrict__ ov = static_cast<T*>(a.vbar);
@@ -256,6 +258,8 @@ template <typename M, int NC, bool FIRST, int RB, int MAXT>
 __global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
+    typedef typename M::acc AT;                 // accumulator type of the products
+    typedef typename Vec4<AT>::type A4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
     constexpr int VPR = 16 / VN;
@@ -334,9 +338,9 @@ __global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
     double gacc[NC + 1];
 #pragma unroll
     for (int k = 0; k <= NC; ++k) gacc[k] = 0.0;
-    T4 acc[RB][NF];
+    A4 acc[RB][NF];
     T4 res[RB][NA];
-    zero<T, RB, NF>(acc);
+    zero<AT, RB, NF>(acc);
     gemm<M, RB, NF>(P, NP, rb0, li, lg, acc, bfrag);
 #pragma unroll
     for (int r = 0; r < RB; ++r)
@@ -369,8 +373,8 @@ __global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
             for (int e = 0; e < 4; ++e) at(q, r, e) = acc[r][q][e] * dc[M::row(lg, e)];
         }
     __syncthreads();
-    T4 acc2[RB][NA];
-    zero<T, RB, NA>(acc2);
+    A4 acc2[RB][NA];
+    zero<AT, RB, NA>(acc2);
     gemm<M, RB, NA>(P, NP, rb0, li, lg, acc2, bfrag);
     T* __restrict__ out0 = static_cast<T*>(a.out0);
     T* __restrict__ out1 = static_cast<T*>(a.out1);

@@ -81,9 +81,13 @@ __device__ __forceinline__ vec_t<T, KL> lds_vec(const T* p) {
 // accumulator register e in lane group g.
 //
 // Native: FP64 or FP32 16x16x4 MFMA, K block 16, four steps of 4.
+//
+// elem is the type of the state (fields, LDS tiles, diagonals, epilogues) and
+// acc the type the matrix cores accumulate in.
 template <typename T>
 struct NativeMma {
     typedef T elem;
+    typedef T acc;
     static constexpr int KB = 16, KL = 4, NSUB = 4;
     static constexpr bool SPLIT_B = false;
     typedef vec_t<T, 4> A;
@@ -96,15 +100,37 @@ struct NativeMma {
     __device__ static int row(int g, int e) { return acc_row<T>(g, e); }
 };
 
+// FP64 state with FP32 products: the fields, the tiles in LDS, the
+// diagonals and every epilogue stay FP64; P is held in FP32 and each B
+// fragment is rounded to FP32 as it is read, for the FP32 16x16x4 MFMA with
+// FP32 accumulation.  The increment form keeps the rounded quantity a
+// correction to the FP64 state.
+struct F64F32Mma {
+    typedef double elem;
+    typedef float acc;
+    static constexpr int KB = 16, KL = 4, NSUB = 4;
+    static constexpr bool SPLIT_B = false;
+    typedef vec_t<float, 4> A;
+    typedef vec_t<float, 4> B;
+    __device__ static A load_a(const void* P, int, long off) {
+        return *reinterpret_cast<const A*>(static_cast<const float*>(P) + off);
+    }
+    __device__ static B prep(const vec_t<double, 4>& b) { return __builtin_convertvector(b, B); }
+    __device__ static void step(vec_t<float, 4>& acc, const A& a, const B& b, int e) { acc = mfma4(a[e], b[e], acc); }
+    __device__ static int row(int g, int e) { return acc_row<float>(g, e); }
+};
+
 // Split BF16: both operands are written x = hi + mid + lo with bfloat16
 // pieces (hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid), each
 // subtraction exact in FP32); the product keeps the six terms whose weight is
 // at least 2^-16 of hi*hi (lo*hi, mid*mid, hi*lo, mid*hi, hi*mid, hi*hi, the
 // small ones first) on the BF16 16x16x32 MFMA with FP32 accumulation.  P's
 // pieces are split once on the host (three planes of NP*NP); the data's are
-// split on the fly.
-struct Bf16x6Mma {
-    typedef float elem;
+// split on the fly (an FP64 state is rounded to FP32 first).
+template <typename S>
+struct Bf16x6MmaOn {
+    typedef S elem;
+    typedef float acc;
     static constexpr int KB = 32, KL = 8, NSUB = 6;
     static constexpr bool SPLIT_B = true;
     struct A {
@@ -122,7 +148,8 @@ struct Bf16x6Mma {
     }
     // Pairs of elements go through two-wide conversions, so that each packed
     // round-to-nearest conversion serves two values and lands in place.
-    __device__ static B prep(const vec_t<float, 8>& x) {
+    __device__ static B prep(const vec_t<S, 8>& xs) {
+        const vec_t<float, 8> x = __builtin_convertvector(xs, vec_t<float, 8>);
         typedef float f2 __attribute__((ext_vector_type(2)));
         typedef __bf16 b2 __attribute__((ext_vector_type(2)));
         B b;
@@ -154,5 +181,6 @@ struct Bf16x6Mma {
     }
     __device__ static int row(int g, int e) { return 4 * g + e; }
 };
+typedef Bf16x6MmaOn<float> Bf16x6Mma;
 
 }  // namespace

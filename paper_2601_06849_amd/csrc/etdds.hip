@@ -76,6 +76,8 @@ const PrecisionOps& ops_for(int precision) {
     switch (precision) {
     case ETD_FP64: return ops_fp64();
     case ETD_FP32: return ops_fp32();
+    case ETD_FP64_FP32: return ops_fp64_fp32();
+    case ETD_FP64_BF16X6: return ops_fp64_bf16x6();
     default: return ops_bf16x6();
     }
 }
@@ -101,7 +103,7 @@ etd_status batch_check(const Batch& B, void* const* u, int nsteps, const void* w
 // (kRedBlocks x 4 doubles), then the four results into res (device).
 etd_status compare_enqueue(const Plan& pl, const void* a, const void* b, double* part, double* res, hipStream_t s) {
     const long n = long(pl.nc) * pl.n[0] * pl.n[1] * pl.n[2];
-    if (pl.prob.precision == ETD_FP64)
+    if (pl.elem == 8)
         hipLaunchKernelGGL(compare_partial<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, s,
                            static_cast<const double*>(a), static_cast<const double*>(b), n, part);
     else

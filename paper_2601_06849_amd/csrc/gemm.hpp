@@ -21,7 +21,7 @@ namespace {
 // this lane's column.
 template <typename M, int RB, int NQ, int PF = 1, typename BL>
 __device__ __forceinline__ void gemm(const void* __restrict__ P, int NP, int rb0, int li, int lg,
-                                     vec_t<typename M::elem, 4> (&acc)[RB][NQ], BL bload) {
+                                     vec_t<typename M::acc, 4> (&acc)[RB][NQ], BL bload) {
     const int nkb = NP / M::KB;
     long off[RB];
 #pragma unroll

@@ -178,7 +178,7 @@ etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
     if (p.rxn < ETD_RXN_NONE || p.rxn > ETD_RXN_FHN_CLASSIC) return bad("unknown reaction");
     if (two != (p.ncomp == 2)) return bad("ncomp must be 2 exactly for the FitzHugh-Nagumo reactions");
     if (p.pade != 0 && p.pade != 2 && p.pade != 4) return bad("pade must be 0 (exact exponentials), 2 or 4");
-    if (p.precision < ETD_FP64 || p.precision > ETD_BF16X6) return bad("unknown precision");
+    if (p.precision < ETD_FP64 || p.precision > ETD_FP64_BF16X6) return bad("unknown precision");
     if (!(p.tau > 0.0) || !std::isfinite(p.tau)) return bad("tau must be a finite positive number");
     if (!(p.q >= 0.0) || !std::isfinite(p.q)) return bad("q must be finite and >= 0");
     for (int c = 0; c < p.ncomp; ++c)
@@ -206,7 +206,7 @@ etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
             err = msg.str();
             return ETD_EUNSUPPORTED;
         }
-    pl.elem = p.precision == ETD_FP64 ? 8 : 4;
+    pl.elem = state_bytes(p.precision);
     for (int d = 0; d < p.dim; ++d) {
         // one component's tile (the split path) must fit; two waves' rows per 16
         const int NP = pl.np[d];
@@ -254,12 +254,12 @@ etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
     // ---- workspace layout ----------------------------------------------------
     Layout& L = pl.lay;
     size_t off = 0;
-    const bool bf = p.precision == ETD_BF16X6;
+    const bool bf = split_bf16(p.precision);
     for (int d = 0; d < 3; ++d) {
         if (d < p.dim) {
             const size_t nn = size_t(pl.np[d]) * pl.np[d];
             L.P[d] = off;
-            L.P_bytes[d] = bf ? 3 * nn * 2 : nn * pl.elem;
+            L.P_bytes[d] = bf ? 3 * nn * 2 : nn * p_bytes(p.precision);
             off = align256(off + L.P_bytes[d]);
         } else {
             L.P[d] = 0;
@@ -267,7 +267,7 @@ etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
         }
     }
     pl.diag_stride = size_t(kMaxPadded);
-    const size_t diag_elem = bf ? 4 : pl.elem;
+    const size_t diag_elem = pl.elem;
     L.diag = off;
     L.diag_bytes = size_t(pl.nc) * kDiagSlots * pl.diag_stride * diag_elem;
     off = align256(off + L.diag_bytes);
@@ -294,9 +294,9 @@ etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
             for (int j = 0; j < n; ++j) {
                 const double v = pl.P[d][size_t(i) * n + j];
                 const size_t idx = size_t(i) * NP + j;
-                if (p.precision == ETD_FP64) {
+                if (!bf && p_bytes(p.precision) == 8) {
                     put<double>(pl.image, L.P[d], idx, v);
-                } else if (p.precision == ETD_FP32) {
+                } else if (!bf) {
                     put<float>(pl.image, L.P[d], idx, float(v));
                 } else {
                     const uint16_t hi = to_bf16(float(v));
@@ -326,7 +326,7 @@ etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
                 else if (slot == kDiagX2) v = p.tau * inc[1];
                 else v = inc[2];
                 const size_t idx = (size_t(c) * kDiagSlots + slot) * pl.diag_stride + j;
-                if (p.precision == ETD_FP64) put<double>(pl.image, L.diag, idx, v);
+                if (pl.elem == 8) put<double>(pl.image, L.diag, idx, v);
                 else put<float>(pl.image, L.diag, idx, float(v));
             }
         }

@@ -43,6 +43,15 @@ inline int rows_per_wave(int NP) { return NP <= 512 ? 2 : 4; }
 inline bool outer_fused(int NP, int nc, size_t elem) { return outer_lds_bytes(NP, 2 * nc, 1, elem) <= kMaxLds; }
 inline bool x_fused(int NP, int nc, size_t elem) { return x_lds_bytes(NP, 2 * nc, 1, elem) <= kMaxLds; }
 
+// Bytes of a state element (fields, tiles, diagonals) and the format of the
+// eigenvector tables, per mode-product precision.
+inline size_t state_bytes(int precision) {
+    return (precision == ETD_FP32 || precision == ETD_BF16X6) ? 4 : 8;
+}
+inline bool split_bf16(int precision) { return precision == ETD_BF16X6 || precision == ETD_FP64_BF16X6; }
+// bytes per entry of a P table that is not split (FP64 products: 8, FP32: 4)
+inline size_t p_bytes(int precision) { return precision == ETD_FP64 ? 8 : 4; }
+
 struct Layout {
     size_t P[3];        // eigenvector matrices (NP x NP, row-major; BF16X6: hi, mid, lo)
     size_t P_bytes[3];

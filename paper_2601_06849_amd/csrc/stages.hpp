@@ -176,6 +176,8 @@ template <typename M, int NC, bool FIRST, int RB, int CB>
 __device__ __forceinline__ void outer_compute(const OuterArgs& a, long tile) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
+    typedef typename M::acc AT;                 // accumulator type of the products
+    typedef typename Vec4<AT>::type A4;
     constexpr int NCOL = 16 * CB;         // columns per tile
     constexpr int NA = 2 * NC;
     constexpr int NQ = NA * CB;           // B fragments per K block
@@ -203,9 +205,9 @@ __device__ __forceinline__ void outer_compute(const OuterArgs& a, long tile) {
     auto at = [&](int qq, int r, int e) -> T& {
         return X[(qq / CB) * AST + ((qq % CB) * 16 + li) * RS + 16 * (rb0 + r) + M::row(lg, e)];
     };
-    T4 acc[RB][NQ];
+    A4 acc[RB][NQ];
     T4 res[RB][NQ];
-    zero<T, RB, NQ>(acc);
+    zero<AT, RB, NQ>(acc);
 
     // ---- forward product S = P g (all arrays share the A operand) ----
     gemm<M, RB, NQ>(P, NP, rb0, li, lg, acc, bfrag);
@@ -228,7 +230,7 @@ __device__ __forceinline__ void outer_compute(const OuterArgs& a, long tile) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) at(qq, r, e) = acc[r][qq][e] * dc[M::row(lg, e)];
         }
-    zero<T, RB, NQ>(acc);
+    zero<AT, RB, NQ>(acc);
     __syncthreads();
 
     // ---- backward product P S and the increment-form epilogue ----
@@ -355,6 +357,8 @@ template <typename M, int NC, int RB, int CB>
 __device__ __forceinline__ void x_compute(const XArgs& a, long tile) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
+    typedef typename M::acc AT;                 // accumulator type of the products
+    typedef typename Vec4<AT>::type A4;
     constexpr int NA = 2 * NC;
     constexpr int NL = 16 * CB;           // lines per tile
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -388,8 +392,8 @@ __device__ __forceinline__ void x_compute(const XArgs& a, long tile) {
     T4 res[RB][NA * CB];
     {
         // ---- b1 = P w3, b2 = P w4 ----
-        T4 acc[RB][NA * CB];
-        zero<T, RB, NA * CB>(acc);
+        A4 acc[RB][NA * CB];
+        zero<AT, RB, NA * CB>(acc);
         gemm<M, RB, NA * CB>(P, NP, rb0, li, lg, acc, bfrag_from(0));
 #pragma unroll
         for (int r = 0; r < RB; ++r)
@@ -417,8 +421,8 @@ __device__ __forceinline__ void x_compute(const XArgs& a, long tile) {
     }
 
     // ---- W = w3 + tau w4 + P c; d = f(W) - w4; V = W + tau d/2 ----
-    T4 acc[RB][NC * CB];
-    zero<T, RB, NC * CB>(acc);
+    A4 acc[RB][NC * CB];
+    zero<AT, RB, NC * CB>(acc);
     gemm<M, RB, NC * CB>(P, NP, rb0, li, lg, acc, bfrag_from(0));
     T4 V[RB][NC * CB];
 #pragma unroll
@@ -447,7 +451,7 @@ __device__ __forceinline__ void x_compute(const XArgs& a, long tile) {
                 }
             }
     }
-    zero<T, RB, NC * CB>(acc);
+    zero<AT, RB, NC * CB>(acc);
     __syncthreads();
 
     // ---- e = (q3 - 1/2) .* (P d) into arrays 0..NC-1 ----
@@ -463,7 +467,7 @@ __device__ __forceinline__ void x_compute(const XArgs& a, long tile) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) at(c, cb, r, e) = d3[M::row(lg, e)] * acc[r][c * CB + cb][e];
         }
-    zero<T, RB, NC * CB>(acc);
+    zero<AT, RB, NC * CB>(acc);
     __syncthreads();
 
     // ---- U+ = V + tau P e ----
@@ -541,6 +545,8 @@ template <typename M, int NC, int KIND, int NW, int QP>
 __global__ __launch_bounds__(64 * NW) void split_product(SplitArgs a) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
+    typedef typename M::acc AT;                 // accumulator type of the products
+    typedef typename Vec4<AT>::type A4;
     constexpr bool YK = KIND <= kSplitYB;   // contracted direction y, columns are x
     constexpr int NARR = (KIND <= kSplitX1) ? 2 * NC : NC;
     static_assert(NARR % QP == 0, "passes must cover the arrays");
@@ -618,7 +624,7 @@ __global__ __launch_bounds__(64 * NW) void split_product(SplitArgs a) {
             return vload(WD, gi + q * sc);
         }
     };
-    T4 acc[NARR / QP][1][QP];
+    A4 acc[NARR / QP][1][QP];
 #pragma unroll
     for (int q0 = 0; q0 < NARR; q0 += QP) {
         // stage arrays q0 .. q0+QP-1 of the tile: X[array][column][k]; all
@@ -655,7 +661,7 @@ __global__ __launch_bounds__(64 * NW) void split_product(SplitArgs a) {
             }
         }
         __syncthreads();
-        zero<T, 1, QP>(acc[q0 / QP]);
+        zero<AT, 1, QP>(acc[q0 / QP]);
         // one wave per SIMD: P fragments are requested four K blocks ahead
         gemm<M, 1, QP, 4>(a.P, NP, rb0, li, lg, acc[q0 / QP],
                        [&](int qq, int k0) { return lds_vec<T, M::KL>(X + qq * AST + li * RS + k0); });
@@ -826,6 +832,8 @@ template <typename M, int RB, int MAXT>
 __global__ __launch_bounds__(MAXT) void x_stage_w(XSplitArgs a) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
+    typedef typename M::acc AT;                 // accumulator type of the products
+    typedef typename Vec4<AT>::type A4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -860,8 +868,8 @@ __global__ __launch_bounds__(MAXT) void x_stage_w(XSplitArgs a) {
     const T* __restrict__ d2 = d1 + a.diag_sstride;
     T4 res[RB][2];
     {
-        T4 acc[RB][2];
-        zero<T, RB, 2>(acc);
+        A4 acc[RB][2];
+        zero<AT, RB, 2>(acc);
         gemm<M, RB, 2>(P, NP, rb0, li, lg, acc, bfrag_from(0));
 #pragma unroll
         for (int r = 0; r < RB; ++r)
@@ -879,8 +887,8 @@ __global__ __launch_bounds__(MAXT) void x_stage_w(XSplitArgs a) {
             }
         __syncthreads();
     }
-    T4 acc[RB][1];
-    zero<T, RB, 1>(acc);
+    A4 acc[RB][1];
+    zero<AT, RB, 1>(acc);
     gemm<M, RB, 1>(P, NP, rb0, li, lg, acc, bfrag_from(0));
     T* __restrict__ o = static_cast<T*>(a.out) + (line0 + li) * NP;
 #pragma unroll
@@ -896,6 +904,8 @@ template <typename M, int RB, int MAXT>
 __global__ __launch_bounds__(MAXT) void x_stage_u(XSplitArgs a) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
+    typedef typename M::acc AT;                 // accumulator type of the products
+    typedef typename Vec4<AT>::type A4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -936,14 +946,14 @@ __global__ __launch_bounds__(MAXT) void x_stage_u(XSplitArgs a) {
     };
     auto at = [&](int q, int r, int e) -> T& { return R[q * AST + li * RS + 16 * (rb0 + r) + M::row(lg, e)]; };
     const T* __restrict__ d3 = static_cast<const T*>(a.diag) + 2 * a.diag_sstride;
-    T4 acc[RB][1];
-    zero<T, RB, 1>(acc);
+    A4 acc[RB][1];
+    zero<AT, RB, 1>(acc);
     gemm<M, RB, 1>(P, NP, rb0, li, lg, acc, bfrag_from(0));
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int e = 0; e < 4; ++e) at(1, r, e) = d3[16 * (rb0 + r) + M::row(lg, e)] * acc[r][0][e];
-    zero<T, RB, 1>(acc);
+    zero<AT, RB, 1>(acc);
     __syncthreads();
     gemm<M, RB, 1>(P, NP, rb0, li, lg, acc, bfrag_from(1));
     const T* __restrict__ Wc = W0 + a.comp * a.sc + (line0 + li) * NP;

@@ -83,5 +83,7 @@ struct PrecisionOps {
 const PrecisionOps& ops_fp64();
 const PrecisionOps& ops_fp32();
 const PrecisionOps& ops_bf16x6();
+const PrecisionOps& ops_fp64_fp32();
+const PrecisionOps& ops_fp64_bf16x6();
 
 }  // namespace etdds

@@ -56,7 +56,7 @@ class Problem:
     lo: tuple = (0.0, 0.0, 0.0)
     hi: tuple = (1.0, 1.0, 1.0)
     pade: int = 2                 # 2: P_{0,2} (Sec. 3.1); 4: P_{0,4} (Sec. 5); 0: exact exponentials (Sec. 2.2)
-    precision: str = "fp64"       # GPU mode-product precision: fp64|fp32|bf16x6
+    precision: str = "fp64"       # GPU mode-product precision: fp64|fp32|bf16x6|fp64_fp32|fp64_bf16x6
 
     def __post_init__(self):
         if self.dim not in (2, 3):

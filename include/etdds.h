@@ -178,8 +178,10 @@ etd_status etd_plan_table(const etd_plan* plan, int which, int d, int comp, doub
  * workspace (etd_adjoint_workspace_bytes bytes, 256-byte aligned, caller-owned);
  * the plan's workspace is used as scratch.  Synchronises `stream`.  Gradients
  * are summed in FP64 in a fixed order.  ETD_EUNSUPPORTED when the adjoint's
- * tiles exceed the on-chip limits (its x tile holds eight fields per
- * component). */
+ * tiles exceed the on-chip limits: they hold four fields of one component,
+ * so padded extents up to 288 with an FP64 state and 576 with an FP32 one
+ * (and the forward x tile of all components must fit, as the replayed steps
+ * keep W). */
 etd_status etd_adjoint_workspace_bytes(const etd_plan* plan, int nsteps, size_t* bytes);
 etd_status etd_adjoint(const etd_plan* plan, const void* u0_dev, double t0, int nsteps, const void* ubar_final_dev,
                        void* ubar0_dev, double* grad, void* workspace_dev, void* adjoint_workspace_dev,

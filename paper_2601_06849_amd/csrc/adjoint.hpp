@@ -10,6 +10,9 @@ namespace {
 // Adjoint driver: sqrt(N) checkpointing
 // ---------------------------------------------------------------------------
 
+// gradient partial-sum arrays of the reverse sweep
+enum AdjPart { kPartXg = 0, kPartXw = 1, kPartY = 2, kPartZ = 3, kPartPoint = 4, kAdjParts = 5 };
+
 struct AdjLayout {
     int K = 1, nck = 1;          // segment length and number of checkpoints
     size_t field = 0;            // bytes per padded field
@@ -19,10 +22,11 @@ struct AdjLayout {
     int slot_fields = 0;
     size_t slots = 0;
     size_t Ub = 0, A[4] = {0, 0, 0, 0};
-    // gradient slots of the x, y and z adjoint kernels and of the pointwise kernel
-    size_t part[4] = {0, 0, 0, 0};
-    long nslots[4] = {0, 0, 0, 0};
-    size_t gsum = 0;             // reduced gradient sums [4][NC + 1]
+    // gradient slots of the two x adjoint kernels, the y and z adjoint
+    // kernels and the pointwise kernel (one per workgroup and component)
+    size_t part[kAdjParts] = {0, 0, 0, 0, 0};
+    long nslots[kAdjParts] = {0, 0, 0, 0, 0};
+    size_t gsum = 0;             // reduced gradient sums [kAdjParts][NC + 1]
     size_t total = 0;
 };
 
@@ -37,14 +41,15 @@ AdjLayout adjoint_layout(const Plan& pl, int nsteps) {
     L.field = pl.lay.field_bytes;
     const int ng = pl.nc + 1;
     const int px = pl.np[0], py = pl.np[1], pz = pl.np[2];
-    L.nslots[0] = long(py) * pz / 16;
+    L.nslots[kPartXg] = long(py) * pz / 16 * pl.nc;
+    L.nslots[kPartXw] = L.nslots[kPartXg];
     if (pl.dim == 3) {
-        L.nslots[1] = long(px) / 16 * pz;
-        L.nslots[2] = long(px) * py / 16;
+        L.nslots[kPartY] = long(px) / 16 * pz * pl.nc;
+        L.nslots[kPartZ] = long(px) * py / 16 * pl.nc;
     } else {
-        L.nslots[1] = long(px) / 16;
+        L.nslots[kPartY] = long(px) / 16 * pl.nc;
     }
-    L.nslots[3] = kPointSlots;
+    L.nslots[kPartPoint] = kPointSlots;
     size_t off = 0;
     L.ck = off;
     off += size_t(L.nck) * L.field;
@@ -59,57 +64,60 @@ AdjLayout adjoint_layout(const Plan& pl, int nsteps) {
         L.A[i] = off;
         off += L.field;
     }
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kAdjParts; ++k) {
         L.part[k] = off;
         off = a256(off + size_t(std::max(L.nslots[k], 1L)) * ng * 8);
     }
     L.gsum = off;
-    off = a256(off + 4 * size_t(ng) * 8);
+    off = a256(off + kAdjParts * size_t(ng) * 8);
     L.total = off;
     return L;
 }
 
-size_t x_adjoint_lds(int NP, int nc, size_t elem) { return x_lds_bytes(NP, 8 * nc, 1, elem); }
-size_t outer_adjoint_lds(int NP, int nc, size_t elem) { return outer_lds_bytes(NP, 4 * nc, 1, elem); }
+// LDS of the adjoint tiles: the x kernels hold four and two fields of one
+// component, the outer kernel four.
+size_t x_adjoint_lds(int NP, size_t elem, bool second) { return x_lds_bytes(NP, second ? 2 : 4, 1, elem); }
+size_t outer_adjoint_lds(int NP, size_t elem) { return outer_lds_bytes(NP, 4, 1, elem); }
 constexpr size_t kStaticLds = 1024;   // the reduction scratch of add_partials
 
 etd_status adjoint_supported(const Plan& pl) {
     const size_t e = pl.elem;
-    if (!x_fused(pl.np[0], pl.nc, e) || x_adjoint_lds(pl.np[0], pl.nc, e) + kStaticLds > kMaxLds)
+    // the replayed forward steps keep W from the fused x stage
+    if (!x_fused(pl.np[0], pl.nc, e) || x_adjoint_lds(pl.np[0], e, false) + kStaticLds > kMaxLds)
         return fail(ETD_EUNSUPPORTED, "the adjoint x tile exceeds the LDS budget at this size, precision and component count");
     for (int d = 1; d < pl.dim; ++d)
-        if (outer_adjoint_lds(pl.np[d], pl.nc, e) + kStaticLds > kMaxLds)
+        if (outer_adjoint_lds(pl.np[d], e) + kStaticLds > kMaxLds)
             return fail(ETD_EUNSUPPORTED, "the adjoint outer tile exceeds the LDS budget at this size and precision");
     return ETD_OK;
 }
 
-template <typename M, int NC, int RB, int MAXT>
+template <typename M, int NC, int RB, int MAXT, bool SECOND>
 etd_status launch_xadj_k(const XAdjArgs& a, long nlines, hipStream_t s) {
     typedef typename M::elem T;
-    const size_t lds = x_adjoint_lds(a.NP, NC, sizeof(T));
-    auto k = x_adjoint<M, NC, RB, MAXT>;
+    const size_t lds = x_adjoint_lds(a.NP, sizeof(T), SECOND);
+    auto k = SECOND ? x_adjoint_w<M, NC, RB, MAXT> : x_adjoint_g<M, NC, RB, MAXT>;
     static size_t done = 0;
     HIP_TRY(set_lds(k, lds, done), "adjoint x LDS attribute");
-    hipLaunchKernelGGL(k, dim3(unsigned(nlines / 16)), dim3(shape_threads(a.NP, RB)), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(unsigned(nlines / 16), unsigned(NC)), dim3(shape_threads(a.NP, RB)), lds, s, a);
     HIP_TRY(hipGetLastError(), "adjoint x launch");
     return ETD_OK;
 }
-#define XADJ_K(RB, MAXT, M, NC, a, nl, s) launch_xadj_k<M, NC, RB, MAXT>(a, nl, s)
+#define XADJ_K(RB, MAXT, M, NC, SECOND, a, nl, s) launch_xadj_k<M, NC, RB, MAXT, SECOND>(a, nl, s)
 
-// Adjoint tiles hold four (outer) or eight (x) fields per component, so at
-// small extents few workgroups fit per CU: one row block per wave up to
-// NP = 128 doubles their waves (the adjoint kernels of a 127^3 two-component
-// FP32 step: 0.335 -> 0.296 ms).
+// Adjoint tiles hold four fields, so at small extents few workgroups fit per
+// CU: one row block per wave up to NP = 128 doubles their waves (the adjoint
+// kernels of a 127^3 two-component FP32 step: 0.335 -> 0.296 ms with the
+// earlier joint tiles).
 #define ADJ_SHAPE(NP, KERNEL, ...) ((NP) <= 128 ? KERNEL(1, 512, __VA_ARGS__) : DISPATCH_SHAPE(NP, KERNEL, __VA_ARGS__))
 
 template <typename M, int NC, bool FIRST, int RB, int MAXT>
 etd_status launch_oadj_k(const OuterAdjArgs& a, long nblocks, hipStream_t s) {
     typedef typename M::elem T;
-    const size_t lds = outer_adjoint_lds(a.NP, NC, sizeof(T));
+    const size_t lds = outer_adjoint_lds(a.NP, sizeof(T));
     auto k = outer_adjoint<M, NC, FIRST, RB, MAXT>;
     static size_t done = 0;
     HIP_TRY(set_lds(k, lds, done), "adjoint outer LDS attribute");
-    hipLaunchKernelGGL(k, dim3(unsigned(nblocks)), dim3(shape_threads(a.NP, RB)), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(unsigned(nblocks), unsigned(NC)), dim3(shape_threads(a.NP, RB)), lds, s, a);
     HIP_TRY(hipGetLastError(), "adjoint outer launch");
     return ETD_OK;
 }
@@ -162,7 +170,7 @@ etd_status adjoint_t(const Plan& pl, StageTimer& tm, const void* u0, double t0, 
     // ---- adjoint state and gradient slots ----
     hipLaunchKernelGGL(pack_field<T>, dim3(2048), dim3(256), 0, s, static_cast<const T*>(ubarN), Ub, dm);
     HIP_TRY(hipGetLastError(), "pack launch");
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kAdjParts; ++k) {
         hipLaunchKernelGGL(fill_zero, dim3(64), dim3(256), 0, s, reinterpret_cast<double*>(aws + L.part[k]),
                            std::max(L.nslots[k], 1L) * ng);
         HIP_TRY(hipGetLastError(), "fill launch");
@@ -188,12 +196,14 @@ etd_status adjoint_t(const Plan& pl, StageTimer& tm, const void* u0, double t0, 
             T* w3 = pl.dim == 3 ? reinterpret_cast<T*>(slot(i, 2)) : w1;
             T* w4 = pl.dim == 3 ? reinterpret_cast<T*>(slot(i, 3)) : w2;
             T* Wf = reinterpret_cast<T*>(slot(i, L.slot_fields - 1));
-            // x direction
+            // x direction: (a) g and the weights h into A[2], A[3]; (b) wbar, vbar into A[0], A[1]
             XAdjArgs xa{};
             xa.ubar = Ub;
             xa.W = Wf;
             xa.w = w3;
             xa.v = w4;
+            xa.g = A[2];
+            xa.h = A[3];
             xa.wbar = A[0];
             xa.vbar = A[1];
             xa.P = ws + pl.lay.P[0];
@@ -205,8 +215,10 @@ etd_status adjoint_t(const Plan& pl, StageTimer& tm, const void* u0, double t0, 
             xa.npy = py;
             xa.tau = tau;
             xa.rxn = rxn_args(pl, ws, tn1);
-            xa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[0]), 0, inv_dim};
-            TRY(ADJ_SHAPE(px, XADJ_K, M, NC, xa, long(py) * pz, s));
+            xa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[kPartXg]), 0, inv_dim};
+            TRY(ADJ_SHAPE(px, XADJ_K, M, NC, false, xa, long(py) * pz, s));
+            xa.grad.partial = reinterpret_cast<double*>(aws + L.part[kPartXw]);
+            TRY(ADJ_SHAPE(px, XADJ_K, M, NC, true, xa, long(py) * pz, s));
             // outer directions
             OuterAdjArgs oa{};
             oa.diag_cstride = dcs;
@@ -221,13 +233,13 @@ etd_status adjoint_t(const Plan& pl, StageTimer& tm, const void* u0, double t0, 
                 oa.P = ws + pl.lay.P[1];
                 oa.diag = diag + long(kDiagY) * dstride;
                 oa.NP = py; oa.ncb = px / 16; oa.sk = px; oa.sb = long(px) * py;
-                oa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[1]), 1, inv_dim};
+                oa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[kPartY]), 1, inv_dim};
                 TRY(ADJ_SHAPE(py, OADJ_K, M, NC, false, oa, long(px / 16) * pz, s));
                 oa.a0 = A[2]; oa.a1 = A[3]; oa.f0 = Un; oa.f1 = nullptr; oa.out0 = A[0]; oa.out1 = A[1];
                 oa.P = ws + pl.lay.P[2];
                 oa.diag = diag + long(kDiagZ) * dstride;
                 oa.NP = pz; oa.ncb = px * py / 16; oa.sk = long(px) * py; oa.sb = 0;
-                oa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[2]), 2, inv_dim};
+                oa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[kPartZ]), 2, inv_dim};
                 TRY(ADJ_SHAPE(pz, OADJ_K, M, NC, true, oa, long(px) * py / 16, s));
                 Lw = A[0];
                 Lv = A[1];
@@ -236,28 +248,32 @@ etd_status adjoint_t(const Plan& pl, StageTimer& tm, const void* u0, double t0, 
                 oa.P = ws + pl.lay.P[1];
                 oa.diag = diag + long(kDiagY) * dstride;
                 oa.NP = py; oa.ncb = px / 16; oa.sk = px; oa.sb = 0;
-                oa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[1]), 1, inv_dim};
+                oa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[kPartY]), 1, inv_dim};
                 TRY(ADJ_SHAPE(py, OADJ_K, M, NC, true, oa, long(px / 16), s));
                 Lw = A[2];
                 Lv = A[3];
             }
             hipLaunchKernelGGL((add_jt_field<T, NC>), dim3(unsigned(kPointSlots)), dim3(256), 0, s, Un, Lw, Lv, Ub,
-                               sc, rxn_args(pl, ws, tn), px, py, reinterpret_cast<double*>(aws + L.part[3]));
+                               sc, rxn_args(pl, ws, tn), px, py, reinterpret_cast<double*>(aws + L.part[kPartPoint]));
             HIP_TRY(hipGetLastError(), "adjoint pointwise launch");
         }
     }
     hipLaunchKernelGGL(unpack_field<T>, dim3(2048), dim3(256), 0, s, Ub, static_cast<T*>(ubar0), dm);
     HIP_TRY(hipGetLastError(), "unpack launch");
     double* gs = reinterpret_cast<double*>(aws + L.gsum);
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kAdjParts; ++k) {
         hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, s, reinterpret_cast<const double*>(aws + L.part[k]),
                            std::max(L.nslots[k], 1L), ng, gs + k * ng);
         HIP_TRY(hipGetLastError(), "gradient reduction launch");
     }
-    double host[4 * 3];
-    HIP_TRY(hipMemcpyAsync(host, gs, 4 * ng * sizeof(double), hipMemcpyDeviceToHost, s), "gradient copy");
+    double host[kAdjParts * 3];
+    HIP_TRY(hipMemcpyAsync(host, gs, kAdjParts * ng * sizeof(double), hipMemcpyDeviceToHost, s), "gradient copy");
     HIP_TRY(hipStreamSynchronize(s), "gradient sync");
-    for (int k = 0; k < ng; ++k) grad[k] = host[k] + host[ng + k] + host[2 * ng + k] + host[3 * ng + k];
+    for (int k = 0; k < ng; ++k) {
+        double t = 0.0;
+        for (int j = 0; j < kAdjParts; ++j) t += host[j * ng + k];
+        grad[k] = t;
+    }
     return ETD_OK;
 }
 

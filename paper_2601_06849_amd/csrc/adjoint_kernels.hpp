@@ -17,10 +17,11 @@ namespace {
 //   dLoss/dp += <Wbar, dQ1x w> + tau <Wbar, dQ2x v> + tau <U+bar, dQ3x d>
 //             + <wbar, dL U> + <vbar, dL f(U)>,     d = f(W) - v,
 // each <a, dQ b> = sum over lines and modes j of (Pa)_j (Pb)_j Q'(tau
-// lambda_j) tau d lambda_j / d p.  The x-direction part and the rest of the
-// step are two fused kernels; each workgroup accumulates its FP64 partial
-// sums [kappa_0 .. kappa_{NC-1}, q] into its own slot (no atomics, so the
-// result is repeatable).
+// lambda_j) tau d lambda_j / d p.  Every adjoint kernel handles one component
+// per workgroup (blockIdx.y); the reaction couples components only pointwise,
+// so the other component enters where a tile is staged.  Each workgroup
+// accumulates its FP64 partial sums [kappa_0 .. kappa_{NC-1}, q] into its own
+// slot (no atomics, so the result is repeatable).
 // ---------------------------------------------------------------------------
 
 struct GradArgs {
@@ -30,10 +31,10 @@ struct GradArgs {
     double inv_dim;       // d lambda / d q
 };
 
-// Block reduction of the lanes' partial sums; adds them into the slot of this
-// workgroup (one writer per slot per launch).
+// Block reduction of the lanes' partial sums; adds them into slot `slot` of
+// the launch (one writer per slot per launch).
 template <int NG>
-__device__ __forceinline__ void add_partials(double (&acc)[NG], double* partial) {
+__device__ __forceinline__ void add_partials(double (&acc)[NG], double* partial, long slot) {
     __shared__ double red[16][NG];
 #pragma unroll
     for (int k = 0; k < NG; ++k) {
@@ -50,17 +51,21 @@ __device__ __forceinline__ void add_partials(double (&acc)[NG], double* partial)
     if (threadIdx.x < NG) {
         double t = 0.0;
         for (int i = 0; i < int(blockDim.x >> 6); ++i) t += red[i][threadIdx.x];
-        partial[long(blockIdx.x) * NG + threadIdx.x] += t;
+        partial[slot * NG + threadIdx.x] += t;
     }
 }
 
+__device__ __forceinline__ long grid_slot() { return long(blockIdx.y) * gridDim.x + blockIdx.x; }
+
 struct XAdjArgs {
-    const void* ubar;     // U+bar, all components (stride sc)
+    const void* ubar;     // U+bar (all components, stride sc)
     const void* W;        // forward W
     const void* w;        // forward w3
     const void* v;        // forward w4
-    void* wbar;           // out: Q1x Wbar
-    void* vbar;           // out: tau Q2x Wbar - g
+    void* g;              // (a) out, (b) in: g = tau Q3x U+bar
+    void* h;              // (a) out, (b) in: spectral weights (P w) rho1 + (P v) rho2
+    void* wbar;           // (b) out: Q1x Wbar
+    void* vbar;           // (b) out: tau Q2x Wbar - g
     const void* P;
     const void* diag;     // slot X1 of component 0
     long diag_sstride, diag_cstride;
@@ -72,18 +77,19 @@ struct XAdjArgs {
     GradArgs grad;
 };
 
-// x-direction adjoint over 16 lines.  LDS: 8*NC fields [16 lines][NP + pad]:
-// ubar, w, v, W (staged), S1 = P ubar, Sw = P w, Sv = P v (own rows), and the
-// scaled coefficients; later slots are reused as noted.
+// x-direction adjoint, part (a), component blockIdx.y over 16 lines.  LDS: 4
+// fields [16 lines][NP + pad]: U+bar, w, v and d = f(W) - v (formed while
+// staging), then (q3 - 1/2) P U+bar.  Writes g and the weights
+// h = (P w) rho1 + (P v) rho2 that part (b) pairs with P Wbar, and adds the
+// <U+bar, dQ3x d> gradient terms.
 template <typename M, int NC, int RB, int MAXT>
-__global__ __launch_bounds__(MAXT) void x_adjoint(XAdjArgs a) {
+__global__ __launch_bounds__(MAXT) void x_adjoint_g(XAdjArgs a) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
-    typedef typename M::acc AT;                 // accumulator type of the products
+    typedef typename M::acc AT;
     typedef typename Vec4<AT>::type A4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
-    constexpr int UB = 0, WW = NC, VV = 2 * NC, FW = 3 * NC, S1 = 4 * NC, SW = 5 * NC, SV = 6 * NC, GS = 7 * NC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* R = reinterpret_cast<T*>(smem_raw);
     const int NP = a.NP;
@@ -93,151 +99,222 @@ __global__ __launch_bounds__(MAXT) void x_adjoint(XAdjArgs a) {
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
+    const int c = blockIdx.y;
     const long line0 = long(blockIdx.x) * 16;
+    const long cs = c * a.sc;
     const void* __restrict__ P = a.P;
     const T tau = T(a.tau);
     const int vpl = NP / VN;
-    const T* src[4] = {static_cast<const T*>(a.ubar), static_cast<const T*>(a.w), static_cast<const T*>(a.v),
-                       static_cast<const T*>(a.W)};
+    const T* ubar = static_cast<const T*>(a.ubar);
+    const T* Wf = static_cast<const T*>(a.W);
+    const T* wf = static_cast<const T*>(a.w);
+    const T* vf = static_cast<const T*>(a.v);
 #pragma unroll 2
     for (int v = tid; v < 16 * vpl; v += blockDim.x) {
         const int j = v / vpl, x = (v - j * vpl) * VN;
         const long gi = line0 * NP + long(v) * VN;
+        const long line = line0 + j;
+        const int y = int(line % a.npy), z = int(line / a.npy);
+        const TV ub = *reinterpret_cast<const TV*>(ubar + cs + gi);
+        const TV ww = *reinterpret_cast<const TV*>(wf + cs + gi);
+        const TV vv = *reinterpret_cast<const TV*>(vf + cs + gi);
+        TV Wk[NC];
 #pragma unroll
-        for (int f = 0; f < 4; ++f)
+        for (int k = 0; k < NC; ++k) Wk[k] = *reinterpret_cast<const TV*>(Wf + k * a.sc + gi);
+        TV d;
 #pragma unroll
-            for (int c = 0; c < NC; ++c)
-                *reinterpret_cast<TV*>(R + (f * NC + c) * AST + j * RS + x) =
-                    *reinterpret_cast<const TV*>(src[f] + c * a.sc + gi);
+        for (int t = 0; t < VN; ++t) {
+            T Wv[NC], F[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) Wv[k] = Wk[k][t];
+            react<T, NC>(a.rxn, Wv, F, x + t, y, z);
+            d[t] = F[c] - vv[t];
+        }
+        *reinterpret_cast<TV*>(R + j * RS + x) = ub;
+        *reinterpret_cast<TV*>(R + AST + j * RS + x) = ww;
+        *reinterpret_cast<TV*>(R + 2 * AST + j * RS + x) = vv;
+        *reinterpret_cast<TV*>(R + 3 * AST + j * RS + x) = d;
     }
     __syncthreads();
     const int rb0 = RB * w;
-    auto bfrag_from = [&](int q0) {
-        return [&, q0](int q, int k0) { return lds_vec<T, M::KL>(R + (q0 + q) * AST + li * RS + k0); };
-    };
+    auto bfrag = [&](int q, int k0) { return lds_vec<T, M::KL>(R + q * AST + li * RS + k0); };
     auto at = [&](int q, int r, int e) -> T& { return R[q * AST + li * RS + 16 * (rb0 + r) + M::row(lg, e)]; };
-    const T* __restrict__ dg = static_cast<const T*>(a.diag);
-    const double* gt = a.grad.table;
-    const long gcs = 3L * kGradSlots * kMaxPadded;   // component stride of the weight table
-
-    // ---- S1 = P ubar, Sw = P w, Sv = P v ----
-    T4 ub[RB][NC];
-    {
-        A4 acc[RB][3 * NC];
-        zero<AT, RB, 3 * NC>(acc);
-        gemm<M, RB, 3 * NC>(P, NP, rb0, li, lg, acc, bfrag_from(0));
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const T* d3 = dg + c * a.diag_cstride + 2 * a.diag_sstride + 16 * (rb0 + r);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    ub[r][c][e] = at(UB + c, r, e);
-                    at(S1 + c, r, e) = acc[r][c][e];
-                    at(SW + c, r, e) = acc[r][NC + c][e];
-                    at(SV + c, r, e) = acc[r][2 * NC + c][e];
-                    at(GS + c, r, e) = d3[M::row(lg, e)] * acc[r][c][e];   // (q3 - 1/2) S1
-                }
-            }
-    }
-    __syncthreads();
-
-    // ---- g = tau (ubar/2 + P ((q3 - 1/2) S1)); d = f(W) - v; Wbar = ubar + J(W)^T g ----
+    const T* __restrict__ d3 = static_cast<const T*>(a.diag) + c * a.diag_cstride + 2 * a.diag_sstride;
+    const double* wt = a.grad.table + c * (3L * kGradSlots * kMaxPadded) + (long(a.grad.dir) * kGradSlots) * kMaxPadded;
+    const long line = line0 + li;
     double gacc[NC + 1];
 #pragma unroll
     for (int k = 0; k <= NC; ++k) gacc[k] = 0.0;
-    T4 g[RB][NC], wb[RB][NC];
+
+    // ---- S1 = P U+bar, Sw = P w, Sv = P v, Sd = P d ----
+    T4 ub[RB];
     {
-        A4 acc[RB][NC];
-        zero<AT, RB, NC>(acc);
-        gemm<M, RB, NC>(P, NP, rb0, li, lg, acc, bfrag_from(GS));
+        A4 acc[RB][4];
+        zero<AT, RB, 4>(acc);
+        gemm<M, RB, 4>(P, NP, rb0, li, lg, acc, bfrag);
+        T* __restrict__ ho = static_cast<T*>(a.h) + cs + line * NP + 16 * rb0;
 #pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                T Wv[NC], F[NC], gg[NC], jt[NC];
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    gg[c] = tau * (T(0.5) * ub[r][c][e] + acc[r][c][e]);
-                    g[r][c][e] = gg[c];
-                    Wv[c] = at(FW + c, r, e);
-                }
-                const long line = line0 + li;
-                const int x = 16 * (rb0 + r) + M::row(lg, e), y = int(line % a.npy), z = int(line / a.npy);
-                react<T, NC>(a.rxn, Wv, F, x, y, z);
-                react_jt<T, NC>(a.rxn, Wv, gg, jt);
-                if (a.rxn.kind == ETD_RXN_AC_MMS) {   // psi(t_{n+1}) depends on kappa and q
-                    const double ue = ac_ue(a.rxn, x, y, z) * double(gg[0]);
-                    gacc[0] += a.rxn.ac_mu * ue;
-                    gacc[NC] += ue;
-                }
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    wb[r][c][e] = ub[r][c][e] + jt[c];
-                    at(UB + c, r, e) = F[c] - at(VV + c, r, e);   // d, over ubar
-                    at(WW + c, r, e) = wb[r][c][e];               // Wbar, over w
-                }
+                const int k = 16 * (rb0 + r) + M::row(lg, e);
+                ub[r][e] = at(0, r, e);
+                const double t3 = double(acc[r][0][e]) * double(acc[r][3][e]) * wt[kGradRho3 * kMaxPadded + k];
+                gacc[c] += t3 * wt[kGradMu * kMaxPadded + k];
+                gacc[NC] += t3 * a.grad.inv_dim;
+                ho[16 * r + M::row(lg, e)] = T(double(acc[r][1][e]) * wt[kGradRho1 * kMaxPadded + k] +
+                                               double(acc[r][2][e]) * wt[kGradRho2 * kMaxPadded + k]);
             }
-    }
-    __syncthreads();
-
-    // ---- Sd = P d, S2 = P Wbar; gradient terms; scaled coefficients of S2 ----
-    {
-        A4 acc[RB][2 * NC];
-        zero<AT, RB, 2 * NC>(acc);
-        gemm<M, RB, 2 * NC>(P, NP, rb0, li, lg, acc, bfrag_from(UB));
+        __syncthreads();
+        // (q3 - 1/2) S1 over U+bar
 #pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const T* d1 = dg + c * a.diag_cstride + 16 * (rb0 + r);
-                const T* d2 = d1 + a.diag_sstride;
-                const double* wt = gt + c * gcs + (long(a.grad.dir) * kGradSlots) * kMaxPadded + 16 * (rb0 + r);
+            for (int e = 0; e < 4; ++e) at(0, r, e) = d3[16 * (rb0 + r) + M::row(lg, e)] * acc[r][0][e];
+    }
+    __syncthreads();
+
+    // ---- g = tau (U+bar / 2 + P ((q3 - 1/2) S1)) ----
+    A4 acc[RB][1];
+    zero<AT, RB, 1>(acc);
+    gemm<M, RB, 1>(P, NP, rb0, li, lg, acc, bfrag);
+    T* __restrict__ go = static_cast<T*>(a.g) + cs + line * NP + 16 * rb0;
+    const int y = int(line % a.npy), z = int(line / a.npy);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int k = M::row(lg, e);
-                    const double sd = acc[r][c][e], s2 = acc[r][NC + c][e];
-                    const double t = s2 * double(at(SW + c, r, e)) * wt[kGradRho1 * kMaxPadded + k] +
-                                     s2 * double(at(SV + c, r, e)) * wt[kGradRho2 * kMaxPadded + k] +
-                                     double(at(S1 + c, r, e)) * sd * wt[kGradRho3 * kMaxPadded + k];
-                    gacc[c] += t * wt[kGradMu * kMaxPadded + k];
-                    gacc[NC] += t * a.grad.inv_dim;
-                    at(VV + c, r, e) = d1[k] * T(s2);   // (q1 - 1) S2, over v
-                    at(FW + c, r, e) = d2[k] * T(s2);   // tau (q2 - 1) S2, over W
-                }
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const T gg = tau * (T(0.5) * ub[r][e] + acc[r][0][e]);
+            go[16 * r + M::row(lg, e)] = gg;
+            if (a.rxn.kind == ETD_RXN_AC_MMS) {   // psi(t_{n+1}) depends on kappa and q
+                const double ue = ac_ue(a.rxn, 16 * (rb0 + r) + M::row(lg, e), y, z) * double(gg);
+                gacc[0] += a.rxn.ac_mu * ue;
+                gacc[NC] += ue;
+            }
+        }
+    add_partials<NC + 1>(gacc, a.grad.partial, grid_slot());
+}
+
+// x-direction adjoint, part (b), component blockIdx.y over 16 lines.  LDS: 2
+// fields: Wbar = U+bar + J(W)^T g (formed while staging), then the scaled
+// coefficients (q1 - 1) P Wbar and tau (q2 - 1) P Wbar.  Adds the
+// <Wbar, dQ1x w> + tau <Wbar, dQ2x v> gradient terms and writes
+// wbar = Q1x Wbar and vbar = tau Q2x Wbar - g.
+template <typename M, int NC, int RB, int MAXT>
+__global__ __launch_bounds__(MAXT) void x_adjoint_w(XAdjArgs a) {
+    typedef typename M::elem T;
+    typedef typename Vec4<T>::type T4;
+    typedef typename M::acc AT;
+    typedef typename Vec4<AT>::type A4;
+    typedef typename Vec16<T>::type TV;
+    constexpr int VN = Vec16<T>::n;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* R = reinterpret_cast<T*>(smem_raw);
+    const int NP = a.NP;
+    const int RS = NP + 16 / int(sizeof(T));
+    const int AST = 16 * RS;
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int li = lane & 15, lg = lane >> 4;
+    const int c = blockIdx.y;
+    const long line0 = long(blockIdx.x) * 16;
+    const long cs = c * a.sc;
+    const void* __restrict__ P = a.P;
+    const T tau = T(a.tau);
+    const int vpl = NP / VN;
+    const T* ubar = static_cast<const T*>(a.ubar);
+    const T* Wf = static_cast<const T*>(a.W);
+    const T* gf = static_cast<const T*>(a.g);
+#pragma unroll 2
+    for (int v = tid; v < 16 * vpl; v += blockDim.x) {
+        const int j = v / vpl, x = (v - j * vpl) * VN;
+        const long gi = line0 * NP + long(v) * VN;
+        const TV ub = *reinterpret_cast<const TV*>(ubar + cs + gi);
+        TV Wk[NC], gk[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            Wk[k] = *reinterpret_cast<const TV*>(Wf + k * a.sc + gi);
+            gk[k] = *reinterpret_cast<const TV*>(gf + k * a.sc + gi);
+        }
+        TV wb;
+#pragma unroll
+        for (int t = 0; t < VN; ++t) {
+            T Wv[NC], gg[NC], jt[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                Wv[k] = Wk[k][t];
+                gg[k] = gk[k][t];
+            }
+            react_jt<T, NC>(a.rxn, Wv, gg, jt);
+            wb[t] = ub[t] + jt[c];
+        }
+        *reinterpret_cast<TV*>(R + j * RS + x) = wb;
+    }
+    __syncthreads();
+    const int rb0 = RB * w;
+    auto bfrag = [&](int q, int k0) { return lds_vec<T, M::KL>(R + q * AST + li * RS + k0); };
+    auto at = [&](int q, int r, int e) -> T& { return R[q * AST + li * RS + 16 * (rb0 + r) + M::row(lg, e)]; };
+    const T* __restrict__ d1 = static_cast<const T*>(a.diag) + c * a.diag_cstride;
+    const T* __restrict__ d2 = d1 + a.diag_sstride;
+    const double* wt = a.grad.table + c * (3L * kGradSlots * kMaxPadded) + (long(a.grad.dir) * kGradSlots) * kMaxPadded;
+    const long line = line0 + li;
+    const long o = cs + line * NP + 16 * rb0;
+    double gacc[NC + 1];
+#pragma unroll
+    for (int k = 0; k <= NC; ++k) gacc[k] = 0.0;
+
+    // ---- S2 = P Wbar; gradient terms against h; scaled coefficients ----
+    T4 wb[RB];
+    {
+        A4 acc[RB][1];
+        zero<AT, RB, 1>(acc);
+        gemm<M, RB, 1>(P, NP, rb0, li, lg, acc, bfrag);
+        const T* __restrict__ hi = static_cast<const T*>(a.h) + o;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = 16 * (rb0 + r) + M::row(lg, e);
+                wb[r][e] = at(0, r, e);
+                const double t = double(acc[r][0][e]) * double(hi[16 * r + M::row(lg, e)]);
+                gacc[c] += t * wt[kGradMu * kMaxPadded + k];
+                gacc[NC] += t * a.grad.inv_dim;
+            }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = 16 * (rb0 + r) + M::row(lg, e);
+                at(0, r, e) = d1[k] * acc[r][0][e];   // (q1 - 1) S2
+                at(1, r, e) = d2[k] * acc[r][0][e];   // tau (q2 - 1) S2
             }
     }
     __syncthreads();
 
     // ---- wbar = Wbar + P ((q1 - 1) S2); vbar = -g + tau Wbar + P (tau (q2 - 1) S2) ----
-    {
-        A4 acc[RB][2 * NC];
-        zero<AT, RB, 2 * NC>(acc);
-        gemm<M, RB, 2 * NC>(P, NP, rb0, li, lg, acc, bfrag_from(VV));
-        T* __restrict__ ow = static_cast<T*>(a.wbar);
-        T* __restrict__ ov = static_cast<T*>(a.vbar);
+    A4 acc[RB][2];
+    zero<AT, RB, 2>(acc);
+    gemm<M, RB, 2>(P, NP, rb0, li, lg, acc, bfrag);
+    T* __restrict__ ow = static_cast<T*>(a.wbar) + o;
+    T* __restrict__ ov = static_cast<T*>(a.vbar) + o;
+    const T* __restrict__ gi = gf + o;
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const long o = c * a.sc + (line0 + li) * NP + 16 * (rb0 + r);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int x = M::row(lg, e);
-                    ow[o + x] = wb[r][c][e] + acc[r][c][e];
-                    ov[o + x] = -g[r][c][e] + tau * wb[r][c][e] + acc[r][NC + c][e];
-                }
-            }
-    }
-    __syncthreads();
-    add_partials<NC + 1>(gacc, a.grad.partial);
+        for (int e = 0; e < 4; ++e) {
+            const int x = 16 * r + M::row(lg, e);
+            ow[x] = wb[r][e] + acc[r][0][e];
+            ov[x] = -gi[x] + tau * wb[r][e] + acc[r][1][e];
+        }
+    add_partials<NC + 1>(gacc, a.grad.partial, grid_slot());
 }
 
 struct OuterAdjArgs {
-    const void* a0;       // adjoint inputs (two fields)
+    const void* a0;       // adjoint inputs (two fields, all components)
     const void* a1;
-    const void* f0;       // forward partners: middle: w1, v1; first: U (f(U) formed here)
+    const void* f0;       // forward partners: middle: w1, w2; first: U (f(U) formed here)
     const void* f1;
     void* out0;           // Q1 a0, Q1 a1
     void* out1;
@@ -251,19 +328,19 @@ struct OuterAdjArgs {
     GradArgs grad;
 };
 
-// Adjoint of an outer stage (z or y): the forward stage applied to the two
-// adjoint fields, plus the gradient terms <a, dQ1 f> against the forward
-// partners.  LDS: 4*NC fields [16 columns][NP + pad]: a0, a1, f0, f1.
+// Adjoint of an outer stage (z or y) for component blockIdx.y: the forward
+// stage applied to the two adjoint fields, plus the gradient terms
+// <a, dQ1 f> against the forward partners.  LDS: 4 fields [16 columns][NP +
+// pad]: a0, a1, f0, f1.
 template <typename M, int NC, bool FIRST, int RB, int MAXT>
 __global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
-    typedef typename M::acc AT;                 // accumulator type of the products
+    typedef typename M::acc AT;
     typedef typename Vec4<AT>::type A4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
     constexpr int VPR = 16 / VN;
-    constexpr int NA = 2 * NC, NF = 4 * NC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* X = reinterpret_cast<T*>(smem_raw);
     const int NP = a.NP;
@@ -273,6 +350,8 @@ __global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
+    const int c = blockIdx.y;
+    const long cs = c * a.sc;
     const int cb = blockIdx.x % a.ncb;
     const long bt = blockIdx.x / a.ncb;
     const long gbase = bt * a.sb + long(cb) * 16;
@@ -285,20 +364,14 @@ __global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
     for (int v = tid; v < NP * VPR; v += blockDim.x) {
         const int k = v / VPR, j0 = (v - k * VPR) * VN;
         const long gi = gbase + long(k) * a.sk + j0;
-        TV fa[NC], fb[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const TV x0 = *reinterpret_cast<const TV*>(a0 + gi + c * a.sc);
-            const TV x1 = *reinterpret_cast<const TV*>(a1 + gi + c * a.sc);
-            fa[c] = *reinterpret_cast<const TV*>(f0 + gi + c * a.sc);
-            if constexpr (!FIRST) fb[c] = *reinterpret_cast<const TV*>(f1 + gi + c * a.sc);
-#pragma unroll
-            for (int t = 0; t < VN; ++t) {
-                X[c * AST + (j0 + t) * RS + k] = x0[t];
-                X[(NC + c) * AST + (j0 + t) * RS + k] = x1[t];
-            }
-        }
+        const TV x0 = *reinterpret_cast<const TV*>(a0 + cs + gi);
+        const TV x1 = *reinterpret_cast<const TV*>(a1 + cs + gi);
+        TV fa, fb;
         if constexpr (FIRST) {
+            TV uk[NC];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) uk[q] = *reinterpret_cast<const TV*>(f0 + q * a.sc + gi);
+            fa = uk[c];
 #pragma unroll
             for (int t = 0; t < VN; ++t) {
                 const int col = cb * 16 + j0 + t;
@@ -314,80 +387,73 @@ __global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
                 }
                 T uu[NC], ff[NC];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) uu[c] = fa[c][t];
+                for (int q = 0; q < NC; ++q) uu[q] = uk[q][t];
                 react<T, NC>(a.rxn, uu, ff, x, y, z);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) fb[c][t] = ff[c];
+                fb[t] = ff[c];
             }
+        } else {
+            fa = *reinterpret_cast<const TV*>(f0 + cs + gi);
+            fb = *reinterpret_cast<const TV*>(f1 + cs + gi);
         }
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int t = 0; t < VN; ++t) {
-                X[(NA + c) * AST + (j0 + t) * RS + k] = fa[c][t];
-                X[(NA + NC + c) * AST + (j0 + t) * RS + k] = fb[c][t];
-            }
+        for (int t = 0; t < VN; ++t) {
+            X[(j0 + t) * RS + k] = x0[t];
+            X[AST + (j0 + t) * RS + k] = x1[t];
+            X[2 * AST + (j0 + t) * RS + k] = fa[t];
+            X[3 * AST + (j0 + t) * RS + k] = fb[t];
+        }
     }
     __syncthreads();
     const int rb0 = RB * w;
     auto bfrag = [&](int q, int k0) { return lds_vec<T, M::KL>(X + q * AST + li * RS + k0); };
     auto at = [&](int q, int r, int e) -> T& { return X[q * AST + li * RS + 16 * (rb0 + r) + M::row(lg, e)]; };
-    const T* __restrict__ dg = static_cast<const T*>(a.diag);
-    const double* gt = a.grad.table;
-    const long gcs = 3L * kGradSlots * kMaxPadded;
+    const T* __restrict__ dc = static_cast<const T*>(a.diag) + c * a.diag_cstride;
+    const double* wt = a.grad.table + c * (3L * kGradSlots * kMaxPadded) + (long(a.grad.dir) * kGradSlots) * kMaxPadded;
     double gacc[NC + 1];
 #pragma unroll
     for (int k = 0; k <= NC; ++k) gacc[k] = 0.0;
-    A4 acc[RB][NF];
-    T4 res[RB][NA];
-    zero<AT, RB, NF>(acc);
-    gemm<M, RB, NF>(P, NP, rb0, li, lg, acc, bfrag);
+    T4 res[RB][2];
+    {
+        A4 acc[RB][4];
+        zero<AT, RB, 4>(acc);
+        gemm<M, RB, 4>(P, NP, rb0, li, lg, acc, bfrag);
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double* wt = gt + c * gcs + (long(a.grad.dir) * kGradSlots) * kMaxPadded + 16 * (rb0 + r);
+        for (int r = 0; r < RB; ++r)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int k = M::row(lg, e);
-                const double t = (double(acc[r][c][e]) * acc[r][NA + c][e] +
-                                  double(acc[r][NC + c][e]) * acc[r][NA + NC + c][e]) *
+                const int k = 16 * (rb0 + r) + M::row(lg, e);
+                const double t = (double(acc[r][0][e]) * acc[r][2][e] + double(acc[r][1][e]) * acc[r][3][e]) *
                                  wt[kGradRho1 * kMaxPadded + k];
                 gacc[c] += t * wt[kGradMu * kMaxPadded + k];
                 gacc[NC] += t * a.grad.inv_dim;
+                res[r][0][e] = at(0, r, e);
+                res[r][1][e] = at(1, r, e);
             }
-        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const T d = dc[16 * (rb0 + r) + M::row(lg, e)];
+                at(0, r, e) = acc[r][0][e] * d;
+                at(1, r, e) = acc[r][1][e] * d;
+            }
+    }
+    __syncthreads();
+    A4 acc[RB][2];
+    zero<AT, RB, 2>(acc);
+    gemm<M, RB, 2>(P, NP, rb0, li, lg, acc, bfrag);
+    T* __restrict__ o0 = static_cast<T*>(a.out0) + cs + gbase + li;
+    T* __restrict__ o1 = static_cast<T*>(a.out1) + cs + gbase + li;
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int q = 0; q < NA; ++q)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) res[r][q][e] = at(q, r, e);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int q = 0; q < NA; ++q) {
-            const T* dc = dg + (q % NC) * a.diag_cstride + 16 * (rb0 + r);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) at(q, r, e) = acc[r][q][e] * dc[M::row(lg, e)];
+        for (int e = 0; e < 4; ++e) {
+            const long row = long(16 * (rb0 + r) + M::row(lg, e)) * a.sk;
+            o0[row] = res[r][0][e] + acc[r][0][e];
+            o1[row] = res[r][1][e] + acc[r][1][e];
         }
-    __syncthreads();
-    A4 acc2[RB][NA];
-    zero<AT, RB, NA>(acc2);
-    gemm<M, RB, NA>(P, NP, rb0, li, lg, acc2, bfrag);
-    T* __restrict__ out0 = static_cast<T*>(a.out0);
-    T* __restrict__ out1 = static_cast<T*>(a.out1);
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int q = 0; q < NA; ++q) {
-            T* o = (q < NC ? out0 : out1) + (q % NC) * a.sc + gbase + li;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) o[long(16 * (rb0 + r) + M::row(lg, e)) * a.sk] = res[r][q][e] + acc2[r][q][e];
-        }
-    __syncthreads();
-    add_partials<NC + 1>(gacc, a.grad.partial);
+    add_partials<NC + 1>(gacc, a.grad.partial, grid_slot());
 }
 
 // Ubar = A + J(U)^T B over a padded field (all components at each node).
@@ -407,7 +473,7 @@ __global__ __launch_bounds__(256) void add_jt_field(const T* __restrict__ U, con
             gacc[0] += r.ac_mu * ue;
             gacc[NC] += ue;
         }
-        add_partials<NC + 1>(gacc, partial);
+        add_partials<NC + 1>(gacc, partial, blockIdx.x);
     }
     for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < npts; i += long(gridDim.x) * blockDim.x) {
         T u[NC], b[NC], jt[NC];

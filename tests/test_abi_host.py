@@ -192,8 +192,9 @@ def test_host_side_argument_errors_touch_nothing(etd):
 
 
 def test_adjoint_workspace_query(etd):
-    """The adjoint's x tile holds eight fields per component; FP64 systems fit
-    up to 64 points in x, FP32 systems up to 128."""
+    """The adjoint's tiles hold four fields of one component: FP64-state
+    systems fit up to 288 points per direction, FP32-state ones up to 576
+    (the forward x tile of two components must also fit, for the replay)."""
     ok = W.Problem(dim=3, n=(127, 127, 127), kappa=(1e-4, 1e-5), tau=0.02, reaction="fhn_cubic", precision="fp32")
     plan = etd.etd_plan_create(ok)
     try:
@@ -205,14 +206,19 @@ def test_adjoint_workspace_query(etd):
         assert ei.value.status == etd.ETD_EINVAL
     finally:
         etd.etd_plan_destroy(plan)
-    big = ok.replace(precision="fp64")
-    plan = etd.etd_plan_create(big)
-    try:
-        with pytest.raises(etd.EtdError) as ei:
-            etd.etd_adjoint_workspace_bytes(plan, 10)
-        assert ei.value.status == etd.ETD_EUNSUPPORTED
-    finally:
-        etd.etd_plan_destroy(plan)
+    for prec, n_ok, n_big in (("fp64", (255, 40, 288), (300, 40, 40)), ("fp64_fp32", (288, 255, 30), (30, 320, 30)),
+                              ("fp32", (511, 40, 576), (40, 640, 40)), ("bf16x6", (576, 30, 30), (30, 30, 700))):
+        for n, good in ((n_ok, True), (n_big, False)):
+            plan = etd.etd_plan_create(ok.replace(n=n, precision=prec))
+            try:
+                if good:
+                    assert etd.etd_adjoint_workspace_bytes(plan, 10) > 0
+                else:
+                    with pytest.raises(etd.EtdError) as ei:
+                        etd.etd_adjoint_workspace_bytes(plan, 10)
+                    assert ei.value.status == etd.ETD_EUNSUPPORTED
+            finally:
+                etd.etd_plan_destroy(plan)
 
 
 def test_tile_shapes_host_validation(etd):

@@ -7,6 +7,9 @@ below 1e-8 at the steps used).  The 3-D FitzHugh-Nagumo workload runs in FP32
 as specified; its gradient is compared with the same FP64 oracle differences
 at a bound derived from FP32 rounding over the run (see the test).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -124,6 +127,28 @@ def test_adjoint_matches_oracle_finite_differences_fp64(etd, oracle_mod, case):
         assert abs(a - b) <= 1e-6 * abs(b), (pname, a, b)
 
 
+@pytest.mark.parametrize("precision,n,N,bound", [
+    ("fp64", (255, 12, 10), 4, 1e-6),        # x padded to 256 (FP64 state)
+    ("fp64", (20, 255, 9), 3, 1e-6),         # y padded to 256
+    ("fp64_fp32", (255, 12, 10), 4, 1e-5),
+    ("fp32", (511, 10, 9), 3, 1e-4),         # x padded to 512 (FP32 state)
+])
+def test_adjoint_large_extents(etd, oracle_mod, precision, n, N, bound):
+    """The adjoint tiles hold four fields of one component, so the adjoint
+    runs up to 256 points per direction with an FP64 state and 512 with an
+    FP32 one.  Two-component 3-D FitzHugh-Nagumo against finite differences
+    of the oracle.  Reduced-precision bounds: the products round to FP32
+    (relative ~6e-8 each, ~1e-7 per step through the operator chain); an FP32
+    state adds the same per step to the forward field and so to U+bar."""
+    p = W.Problem(dim=3, n=n, kappa=(0.004, 0.001), q=0.2, tau=0.02, reaction="fhn_cubic",
+                  rxn_param=(0.1, 0.01, 0.5), precision=precision)
+    u0 = W.u0_fhn_patch(p, 7, patch=0.5)
+    rows = adjoint_vs_fd(etd, oracle_mod, p, u0, 0.8 * u0, N,
+                         fd_precision="extended" if precision == "fp64" else "fp64")
+    for pname, a, b in rows:
+        assert abs(a - b) <= bound * abs(b), (pname, a, b)
+
+
 def test_adjoint_fhn3d_n127_fp32(etd, oracle_mod):
     """The 3-D FitzHugh-Nagumo workload (127^3, FP32) over 40 of its steps;
     loss = 1/2 ||u(T) - u_target||^2 with u_target from a run at 1.1 kappa_u.
@@ -141,6 +166,75 @@ def test_adjoint_fhn3d_n127_fp32(etd, oracle_mod):
     rows = adjoint_vs_fd(etd, oracle_mod, p, u0, target, N, fd_precision="fp64")
     for pname, a, b in rows:
         assert abs(a - b) <= 1e-3 * abs(b), (pname, a, b)
+
+
+FD_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fhn3d_n127_fd.json")
+_FHN3D_TARGET = {}
+
+
+def fhn3d_target(oracle_mod, g):
+    """u_target of the 400-step gradient workload: the oracle's u_N at
+    1.1 kappa_u (computed once per session)."""
+    if "t" not in _FHN3D_TARGET:
+        wl = W.fhn3d()
+        p = wl.problem.replace(precision="fp64")
+        _FHN3D_TARGET["t"] = oracle_mod.advance(
+            p.replace(kappa=(p.kappa[0] * g["target_kappa_scale"], p.kappa[1])), wl.u0(), g["nsteps"])
+    return _FHN3D_TARGET["t"]
+
+
+# relative bound per precision: FP64 at the north star's 1e-6; the reduced
+# modes at bounds derived from their rounding (see the test's docstring;
+# measured: FP64 <= 6.8e-8, FP64 state with FP32 products <= 1.3e-6, FP32
+# state <= 8.2e-6)
+FHN3D_BOUNDS = {"fp64": 1e-6, "fp64_fp32": 1e-5, "fp32": 1e-4}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp64_fp32", "fp32"])
+def test_adjoint_fhn3d_n127_all_400_steps(etd, oracle_mod, precision):
+    """The 3-D FitzHugh-Nagumo gradient workload over all 400 steps (127^3 x
+    2, tau = 0.02, sqrt(N) = 20-step checkpoint segments): dL/dkappa_u,
+    dL/dkappa_v, dL/dq and dL/du0 along a seeded direction against central
+    finite differences of the FP64 oracle (tests/golden/fhn3d_n127_fd.json,
+    written by tests/golden/make_fhn3d_fd.py from the oracle alone).
+
+    FP64: <= 1e-6 (the differences' truncation is ~1e-8).  The loss is
+    ill-conditioned for reduced precision: u_N - u_target is only 1.3% of
+    u_N (residual_rel in the golden file), and every gradient is linear in
+    U+bar = u_N - u_target, so a relative forward error e of u_N can become
+    e / 0.013 in the gradients.  FP32 products on an FP64 state leave
+    e ~ 5e-8 (the 2-D workload's 2000 steps: 5.2e-8), so up to ~4e-6; an
+    FP32 state adds ~6e-8 per step of rounding (e ~ 2.5e-7 after 40 steps,
+    growing with the run), so a few 1e-5.  The bounds take those amplified
+    errors with a factor ~2-4 of margin."""
+    import torch
+    with open(FD_GOLDEN) as f:
+        g = json.load(f)
+    wl = W.fhn3d(precision=precision)
+    p = wl.problem
+    u0 = wl.u0()
+    N = g["nsteps"]
+    assert N == wl.nsteps and list(p.kappa) == g["kappa"] and p.q == g["q"]
+    target = fhn3d_target(oracle_mod, g)
+    st = etd.Stepper(p)
+    u = st.field(u0)
+    st.advance(u, N)
+    torch.cuda.synchronize()
+    uN = u.cpu().numpy().astype(np.float64)
+    ubar = uN - target
+    ubar0, grad = st.adjoint(st.field(u0), st.field(ubar), N)
+    ubar0 = ubar0.cpu().numpy().astype(np.float64)
+    st.close()
+    dl = np.random.default_rng(g["dir_seed"]).standard_normal(u0.shape)
+    got = {"kappa0": grad[0], "kappa1": grad[1], "q": grad[2], "u0_dir": float((ubar0 * dl).sum())}
+    fwd = float(np.linalg.norm(uN - target) / np.linalg.norm(uN))
+    print(f"  {precision}: residual_rel {fwd:.3e} (oracle {g['residual_rel']:.3e})")
+    bound = FHN3D_BOUNDS[precision]
+    for name, ref in g["gradient"].items():
+        rel = abs(got[name] - ref) / abs(ref)
+        print(f"  {precision} {name}: adjoint {got[name]:.10e} fd {ref:.10e} rel {rel:.2e}")
+    for name, ref in g["gradient"].items():
+        assert abs(got[name] - ref) <= bound * abs(ref), (name, got[name], ref)
 
 
 def test_autograd_function_matches_adjoint(etd):

@@ -92,6 +92,9 @@ struct NativeMma {
     static constexpr bool SPLIT_B = false;
     typedef vec_t<T, 4> A;
     typedef vec_t<T, 4> B;
+    // row-major P: lane (i, g) of row block rb reads P[16 rb + i][KL g ..]
+    __device__ static long a_off(int NP, int rb, int li, int lg) { return long(16 * rb + li) * NP + KL * lg; }
+    __device__ static long a_kstep(int) { return KB; }
     __device__ static A load_a(const void* P, int, long off) {
         return *reinterpret_cast<const A*>(static_cast<const T*>(P) + off);
     }
@@ -112,6 +115,8 @@ struct F64F32Mma {
     static constexpr bool SPLIT_B = false;
     typedef vec_t<float, 4> A;
     typedef vec_t<float, 4> B;
+    __device__ static long a_off(int NP, int rb, int li, int lg) { return long(16 * rb + li) * NP + KL * lg; }
+    __device__ static long a_kstep(int) { return KB; }
     __device__ static A load_a(const void* P, int, long off) {
         return *reinterpret_cast<const A*>(static_cast<const float*>(P) + off);
     }
@@ -125,8 +130,12 @@ struct F64F32Mma {
 // subtraction exact in FP32); the product keeps the six terms whose weight is
 // at least 2^-16 of hi*hi (lo*hi, mid*mid, hi*lo, mid*hi, hi*mid, hi*hi, the
 // small ones first) on the BF16 16x16x32 MFMA with FP32 accumulation.  P's
-// pieces are split once on the host (three planes of NP*NP); the data's are
-// split on the fly (an FP64 state is rounded to FP32 first).
+// pieces are split once on the host and stored in fragment order: for row
+// block rb and K block kb, one contiguous chunk of three planes (hi, mid, lo)
+// x 64 lanes x 8 values, lane i + 16 g holding P[16 rb + i][32 kb + 8 g ..
+// +8], so each plane of a fragment is one fully used 1 KB run (row-major
+// planes would touch sixteen half-used lines per load).  The data's pieces
+// are split on the fly (an FP64 state is rounded to FP32 first).
 template <typename S>
 struct Bf16x6MmaOn {
     typedef S elem;
@@ -137,13 +146,17 @@ struct Bf16x6MmaOn {
         bf16x8 p[3];   // hi, mid, lo
     };
     typedef A B;
-    __device__ static A load_a(const void* P, int NP, long off) {
+    static constexpr int CHUNK = 3 * 64 * 8;   // bf16 values per (row block, K block)
+    __device__ static long a_off(int NP, int rb, int li, int lg) {
+        return long(rb) * (NP / KB) * CHUNK + 8 * (li + 16 * lg);
+    }
+    __device__ static long a_kstep(int) { return CHUNK; }
+    __device__ static A load_a(const void* P, int, long off) {
         const __bf16* q = static_cast<const __bf16*>(P) + off;
-        const long plane = long(NP) * NP;
         A a;
         a.p[0] = *reinterpret_cast<const bf16x8*>(q);
-        a.p[1] = *reinterpret_cast<const bf16x8*>(q + plane);
-        a.p[2] = *reinterpret_cast<const bf16x8*>(q + 2 * plane);
+        a.p[1] = *reinterpret_cast<const bf16x8*>(q + 512);
+        a.p[2] = *reinterpret_cast<const bf16x8*>(q + 1024);
         return a;
     }
     // Pairs of elements go through two-wide conversions, so that each packed

@@ -11,8 +11,9 @@ namespace {
 // ---------------------------------------------------------------------------
 
 // acc[r][q] += P[16(rb0+r) .. +16][:] . B_q over the whole contracted length
-// NP (a multiple of M::KB).  The A operand comes straight from the row-major P
-// in global memory (L2-resident; each lane reads its KL contiguous entries)
+// NP (a multiple of M::KB).  The A operand comes straight from P in global
+// memory (L2-resident; M::a_off / a_kstep give a lane's first fragment and the
+// step to the next K block: row-major P, or a fragment-ordered copy)
 // and is held in a ring of PF register buffers, so each K block's fragment is
 // requested PF blocks before its use (PF = 1: one block ahead; launches with
 // one wave per SIMD need a deeper ring to cover the L2 latency, and there
@@ -23,15 +24,16 @@ template <typename M, int RB, int NQ, int PF = 1, typename BL>
 __device__ __forceinline__ void gemm(const void* __restrict__ P, int NP, int rb0, int li, int lg,
                                      vec_t<typename M::acc, 4> (&acc)[RB][NQ], BL bload) {
     const int nkb = NP / M::KB;
+    const long kstep = M::a_kstep(NP);
     long off[RB];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) off[r] = long(16 * (rb0 + r) + li) * NP + M::KL * lg;
+    for (int r = 0; r < RB; ++r) off[r] = M::a_off(NP, rb0 + r, li, lg);
     // ring[i] holds K block kb + i (addresses clamp to the last block)
     typename M::A ring[PF][RB];
 #pragma unroll
     for (int i = 0; i < PF; ++i)
 #pragma unroll
-        for (int r = 0; r < RB; ++r) ring[i][r] = M::load_a(P, NP, off[r] + min(i, nkb - 1) * M::KB);
+        for (int r = 0; r < RB; ++r) ring[i][r] = M::load_a(P, NP, off[r] + min(i, nkb - 1) * kstep);
     // with a ring (PF > 1) FP64 B fragments are also read one K block ahead
     // (measured: 2% on the FP64 2-D kernels; FP32 fragments gain nothing)
     constexpr bool BNEXT = PF > 1 && !M::SPLIT_B && sizeof(typename M::elem) == 8;
@@ -48,7 +50,7 @@ __device__ __forceinline__ void gemm(const void* __restrict__ P, int NP, int rb0
             typename M::A a_cur[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) a_cur[r] = ring[i][r];
-            const int kn = min(kb + PF, nkb - 1) * M::KB;
+            const long kn = min(kb + PF, nkb - 1) * kstep;
 #pragma unroll
             for (int r = 0; r < RB; ++r) ring[i][r] = M::load_a(P, NP, off[r] + kn);
             if constexpr (M::SPLIT_B) {

@@ -530,7 +530,8 @@ StepArgs step_args(const Plan& pl, char* ws, const void* const Pdir[3]) {
     return a;
 }
 
-// One product-parallel launch: row groups of 16*NW rows x 16-column tiles.
+// One product-parallel launch: row groups of 16*NW rows x 16-column tiles,
+// as a one-dimensional grid (split_block maps it XCD by XCD).
 template <typename M, int NC, int KIND, int NW, int QP>
 etd_status launch_split_k(const SplitArgs& a, long ncols, hipStream_t s) {
     typedef typename M::elem T;
@@ -538,7 +539,7 @@ etd_status launch_split_k(const SplitArgs& a, long ncols, hipStream_t s) {
     auto k = split_product<M, NC, KIND, NW, QP>;
     static size_t done = 0;
     HIP_TRY(set_lds(k, lds, done), "2-D product LDS attribute");
-    hipLaunchKernelGGL(k, dim3(unsigned(a.NP / (16 * NW)), unsigned(ncols / 16)), dim3(64 * NW), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(unsigned(a.NP / (16 * NW) * (ncols / 16))), dim3(64 * NW), lds, s, a);
     HIP_TRY(hipGetLastError(), "2-D product launch");
     return ETD_OK;
 }

@@ -289,7 +289,6 @@ etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
     pl.image.assign(pl.table_bytes, 0);
     for (int d = 0; d < p.dim; ++d) {
         const int n = pl.n[d], NP = pl.np[d];
-        const size_t nn = size_t(NP) * NP;
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) {
                 const double v = pl.P[d][size_t(i) * n + j];
@@ -304,9 +303,15 @@ etd_status build_plan(const etd_problem& p, Plan& pl, std::string& err) {
                     const uint16_t mid = to_bf16(float(r1));
                     const double r2 = r1 - from_bf16(mid);
                     const uint16_t lo = to_bf16(float(r2));
-                    put<uint16_t>(pl.image, L.P[d], idx, hi);
-                    put<uint16_t>(pl.image, L.P[d], nn + idx, mid);
-                    put<uint16_t>(pl.image, L.P[d], 2 * nn + idx, lo);
+                    // fragment order of the split-BF16 A operand: chunk (row
+                    // block i/16, K block j/32) of 3 planes x 64 lanes x 8
+                    // values, lane (i%16) + 16 ((j%32)/8), value j%8
+                    const size_t chunk = (size_t(i / 16) * (NP / 32) + size_t(j / 32)) * (3 * 64 * 8);
+                    const size_t lane = size_t(i % 16) + 16 * size_t((j % 32) / 8);
+                    const size_t at = chunk + lane * 8 + size_t(j % 8);
+                    put<uint16_t>(pl.image, L.P[d], at, hi);
+                    put<uint16_t>(pl.image, L.P[d], at + 512, mid);
+                    put<uint16_t>(pl.image, L.P[d], at + 1024, lo);
                 }
             }
     }

@@ -539,6 +539,19 @@ struct SplitArgs {
     RxnArgs rxn;          // at t_n (y kinds) or t_{n+1} (x kinds)
 };
 
+// Row group and column tile of workgroup L of a product-parallel launch
+// (nrg row groups x T / nrg column tiles, T workgroups).  The dispatcher deals
+// consecutive workgroups to the eight XCDs in turn (XCD = L % 8), and every
+// row group of a column tile stages the same B panel, so each XCD takes a
+// contiguous run of column tiles with all their row groups: the panel comes
+// from HBM once and from that XCD's L2 for the other row groups.
+__device__ __forceinline__ void split_block(int nrg, int T, int L, int& rg, int& ct) {
+    int t = L;
+    if (T % 8 == 0) t = (L % 8) * (T / 8) + L / 8;
+    rg = t % nrg;
+    ct = t / nrg;
+}
+
 // QP arrays are staged per pass (as many as the LDS holds), so each P
 // fragment feeds QP MFMAs per step.
 template <typename M, int NC, int KIND, int NW, int QP>
@@ -558,8 +571,10 @@ __global__ __launch_bounds__(64 * NW) void split_product(SplitArgs a) {
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
-    const int rb0 = int(blockIdx.x) * NW + w;   // this wave's 16-row block
-    const int col0 = int(blockIdx.y) * 16;
+    int rg, ct;
+    split_block(a.NP / (16 * NW), int(gridDim.x), int(blockIdx.x), rg, ct);
+    const int rb0 = rg * NW + w;   // this wave's 16-row block
+    const int col0 = ct * 16;
     const long sc = a.sc;
     T* U = static_cast<T*>(a.U);
     T* WA = static_cast<T*>(a.WA);

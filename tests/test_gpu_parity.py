@@ -176,14 +176,18 @@ def test_fhn2d_n511_fp32_against_fp64_oracle(etd, oracle_mod):
     assert_close(got, fhn2d_reference(oracle_mod), 1e-5, "2000 steps")
 
 
-def test_fhn3d_n127_fp32_against_fp64_oracle(etd, oracle_mod):
-    """3-D FitzHugh-Nagumo, 127^3, FP32 products and state, 40 of its 400 steps."""
+_FHN3D_REF = {}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64_fp32", "fp64"])
+def test_fhn3d_n127_whole_run(etd, oracle_mod, precision):
+    """3-D FitzHugh-Nagumo, 127^3 x 2 (the gradient workload's forward map),
+    all 400 steps against the FP64 oracle: the state the adjoint starts from."""
     wl = W.fhn3d()
-    ref = oracle_mod.advance(wl.problem.replace(precision="fp64"), wl.u0(), 40)
-    got = run_gpu(etd, wl.problem, wl.u0(), 40)
-    err = rel_l2(got, ref)
-    print(f"  fp32 rel_l2 vs fp64 oracle = {err:.3e}")
-    assert err <= REDUCED_TOL
+    if "ref" not in _FHN3D_REF:
+        _FHN3D_REF["ref"] = oracle_mod.advance(wl.problem.replace(precision="fp64"), wl.u0(), wl.nsteps)
+    got = run_gpu(etd, wl.problem.replace(precision=precision), wl.u0(), wl.nsteps)
+    assert_close(got, _FHN3D_REF["ref"], FP64_TOL if precision == "fp64" else REDUCED_TOL, precision)
 
 
 @pytest.mark.parametrize("n", [127, 255, 511, 1023])

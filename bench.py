@@ -38,7 +38,10 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-point updates/sec (m^d x steps) at 3D m=255, FP64 vs reduced at <=1e-6"
 # dense matrix-core peaks (MI355X datasheet); split-BF16 products are priced
 # at the BF16 rate, six MFMA terms per product
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x6": 2500.0 / 6}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x6": 2500.0 / 6, "fp64_fp32": 157.3, "fp64_bf16x6": 2500.0 / 6}
+PRECISIONS = ["fp64", "fp32", "bf16x6", "fp64_fp32", "fp64_bf16x6"]
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x6": "bf16x6->f32", "fp64_fp32": "f64 state, f32 products",
+         "fp64_bf16x6": "f64 state, bf16x6->f32 products"}
 STAGE_NAMES = ("z_stage", "y_stage", "x_stage")
 # mode products per launch of each stage kind (3-D): z and y apply Q1 to two
 # fields (forward + back each), the fused x stage does five products
@@ -50,11 +53,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x6"])
-    ap.add_argument("--reduced", default="fp32,bf16x6",
+    ap.add_argument("--precision", default="fp64", choices=PRECISIONS)
+    ap.add_argument("--repeats", type=int, default=5, help="timed repetitions of --steps steps (median reported)")
+    ap.add_argument("--settle-blocks", type=int, default=10,
+                    help="at most this many 20-step warm-up blocks until the step time settles (0: none)")
+    ap.add_argument("--reduced", default="fp32,bf16x6,fp64_fp32,fp64_bf16x6",
                     help="comma-separated reduced-precision variants timed beside fp64, or 'none'")
     ap.add_argument("--cpu-steps", type=int, default=10)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=255)
     ap.add_argument("--adjoint-steps", type=int, default=400)
@@ -67,26 +73,53 @@ def parse():
     return ap.parse_args()
 
 
-def timed_run(etd, torch, wl, precision, steps, warmup):
-    """Warm up, then time `steps` steps from the workload's u0.  Returns the
-    final field, wall seconds and the per-stage event timings."""
+SETTLE_BLOCKS = 10
+
+
+def timed_run(etd, torch, wl, precision, steps, warmup, repeats=5):
+    """Warm up, then time `steps` steps from the workload's u0, `repeats` times
+    without per-stage events (the value is the median), then once more with
+    per-stage HIP events (the roofline's per-kernel launch times).  Warm-up:
+    `warmup` steps, then further 20-step blocks until two consecutive blocks
+    agree within 1% (clocks settled; at most --settle-blocks blocks).  Returns the final
+    field of the first repetition, the median wall seconds, all repetition
+    times and the event timings."""
     p = wl.problem.replace(precision=precision)
     st = etd.Stepper(p)
     u0 = wl.u0()
     u = st.field(u0)
     if warmup:
         st.advance(u, warmup)
+    prev = None
+    for _ in range(SETTLE_BLOCKS):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.advance(u, 20)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if prev is not None and abs(dt - prev) <= 0.01 * prev:
+            break
+        prev = dt
+    times = []
+    first = None
+    for r in range(repeats):
+        u = st.field(u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.advance(u, steps)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        if first is None:
+            first = u
     u = st.field(u0)
     etd.etd_timing_enable(st.plan, True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     st.advance(u, steps)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     ms, counts = etd.etd_timing_read(st.plan)
     etd.etd_timing_enable(st.plan, False)
     st.close()
-    return u, t1 - t0, ms, counts
+    return first, sorted(times)[len(times) // 2], times, ms, counts
 
 
 CSRC = os.path.join(ROOT, "paper_2601_06849_amd", "csrc")
@@ -238,27 +271,31 @@ def latency_leg(etd, torch, W, nsteps):
             "graph_us_per_step": 1e6 * graph / nsteps}
 
 
-def fhn2d_leg(etd, torch, W, nsteps):
+def fhn2d_leg(etd, torch, W, nsteps, repeats=5):
     """2-D coupled FitzHugh-Nagumo, 511^2 x 2 components (the product-parallel
-    2-D path): FP64 and FP32 over the same steps from the same u0, timed
-    without per-stage events (a step is only about 0.1-0.2 ms), then the same
-    steps replayed from a captured HIP graph.  Useful work is 18 n^3 flops per
-    component and step (nine mode products)."""
+    2-D path): FP64 and the reduced-product precisions over the same steps
+    from the same u0, timed without per-stage events (a step is only about
+    0.1-0.2 ms; median of `repeats`), then the same steps replayed from a
+    captured HIP graph.  Useful work is 18 n^3 flops per component and step
+    (nine mode products)."""
     out = {"workload": "fhn2d_n511", "steps": nsteps}
     final = {}
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "fp64_fp32", "fp64_bf16x6"):
         wl = W.fhn2d(precision=prec)
         n = wl.problem.n[0]
         st = etd.Stepper(wl.problem)
         u0 = wl.u0()
-        st.advance(st.field(u0), 5)
-        u = st.field(u0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st.advance(u, nsteps)
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - t0
-        final[prec] = u.clone()
+        st.advance(st.field(u0), 20)
+        times = []
+        for _ in range(repeats):
+            u = st.field(u0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st.advance(u, nsteps)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            final.setdefault(prec, u.clone())
+        sec = sorted(times)[len(times) // 2]
         # the same steps captured once in a HIP graph and replayed
         s = torch.cuda.Stream()
         g = st.capture(u, nsteps, s)
@@ -274,9 +311,53 @@ def fhn2d_leg(etd, torch, W, nsteps):
         out[prec] = {"ms_per_step": 1e3 * sec / nsteps, "value": n * n * nsteps / sec,
                      "useful_tflops": useful / sec / 1e12, "frac_of_peak": useful / sec / 1e12 / PEAK_TFLOPS[prec],
                      "graph_ms_per_step": 1e3 * gsec / nsteps}
-    out["fp32"]["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
-    out["fp32"]["rel_l2_vs_fp64"] = float((final["fp32"].double() - final["fp64"]).norm() / final["fp64"].norm())
+    for prec in ("fp32", "fp64_fp32", "fp64_bf16x6"):
+        d = final[prec].double() - final["fp64"]
+        out[prec]["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out[prec]["ms_per_step"]
+        out[prec]["rel_l2_vs_fp64"] = float(d.norm() / final["fp64"].norm())
+        out[prec]["rel_max_vs_fp64"] = float(d.abs().max() / final["fp64"].abs().max())
     return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, args):
+    """The oracle as it stands, on a bounded sample of the same workload: with
+    all host threads, chunks of --cpu-steps steps from u0 until about
+    --cpu-seconds of host time (three chunks at least; the value is the median
+    chunk rate), then one chunk on one thread."""
+    import oracle
+    p = wl.problem.replace(precision="fp64")
+    npts = wl.problem.npoints
+    cores = oracle.threads(0)
+    u = wl.u0()
+    done, spent, rates = 0, 0.0, []
+    while (spent < args.cpu_seconds or len(rates) < 3) and done < 400:
+        t0 = time.perf_counter()
+        u = oracle.advance(p, u, args.cpu_steps, t0=done * p.tau, nthreads=0)
+        dt = time.perf_counter() - t0
+        spent += dt
+        done += args.cpu_steps
+        rates.append(npts * args.cpu_steps / dt)
+    t0 = time.perf_counter()
+    oracle.advance(p, wl.u0(), 1, nthreads=1)
+    one = time.perf_counter() - t0
+    return {"value": sorted(rates)[len(rates) // 2], "unit": "grid-point updates/s", "cores": cores,
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "chunk_rate_range": [min(rates), max(rates)],
+            "statistic": f"median of {len(rates)} chunks of {args.cpu_steps} steps",
+            "one_thread": {"value": npts / one, "sample": f"1 step of {wl.name} on 1 thread in {one:.1f} s"},
+            "sample": f"first {done} steps of {wl.name} from the same u0 in {spent:.1f} s on {cores} threads "
+                      f"(FP64 complex Thomas line solves, OpenMP over lines)"}
 
 
 def main():
@@ -301,9 +382,12 @@ def main():
     import paper_2601_06849_amd as etd
     import workloads as W
 
+    global SETTLE_BLOCKS
+    SETTLE_BLOCKS = args.settle_blocks
+
     wl = W.fisher3d(precision=args.precision, n=args.n, nsteps=args.steps)
     npts = wl.problem.npoints
-    u_main, sec, ms, counts = timed_run(etd, torch, wl, args.precision, args.steps, args.warmup)
+    u_main, sec, times, ms, counts = timed_run(etd, torch, wl, args.precision, args.steps, args.warmup, args.repeats)
     value = npts * args.steps / sec
     roof, stages = roofline(wl, args.precision, ms, counts)
     useful = 26.0 * args.n ** 4 * args.steps  # 13 mode products per 3-D step
@@ -319,11 +403,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x6": "bf16x6->f32"}[args.precision],
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": [args.n] * 3, "kappa": wl.problem.kappa[0], "q": wl.problem.q,
                    "tau": wl.problem.tau, "reaction": "u(1-u)", "precision": args.precision,
                    "init": "sine product + 8 Gaussian bumps (sigma 0.05), seed %d" % wl.seed},
+        "timing": {"repeats": args.repeats, "statistic": "median of the repeats, each exactly --steps steps "
+                   "from u0, no per-stage events; the roofline comes from one further repeat with per-stage "
+                   "HIP events", "ms_per_step_repeats": [1e3 * t / args.steps for t in times]},
         "roofline": roof,
         "stages": stages,
         "useful_tflops": useful / sec / 1e12,
@@ -334,12 +421,15 @@ def main():
         # FP64 result they are compared with matches the FP64 oracle to 1e-12
         out["reduced"] = {}
         for prec in args.reduced.split(","):
-            u_red, sec_r, ms_r, counts_r = timed_run(etd, torch, wl, prec, args.steps, args.warmup)
-            diff = (u_red.double() - u_main).norm() / u_main.norm()
+            u_red, sec_r, _, ms_r, counts_r = timed_run(etd, torch, wl, prec, args.steps, args.warmup,
+                                                        args.repeats)
+            d = u_red.double() - u_main
             roof_r, _ = roofline(wl, prec, ms_r, counts_r)
             out["reduced"][prec] = {"value": npts * args.steps / sec_r, "ms_per_step": 1e3 * sec_r / args.steps,
-                                    "speedup_vs_fp64": sec / sec_r, "rel_l2_vs_fp64": float(diff),
-                                    "roofline": roof_r}
+                                    "speedup_vs_fp64": sec / sec_r,
+                                    "rel_l2_vs_fp64": float(d.norm() / u_main.norm()),
+                                    "rel_max_vs_fp64": float(d.abs().max() / u_main.abs().max()),
+                                    "dtype": DTYPE[prec], "roofline": roof_r}
 
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint_leg(etd, torch, W, args.adjoint_steps)
@@ -351,9 +441,9 @@ def main():
         # same kernels, exact-exponential diagonals; compared with the Pade
         # result after the same steps from the same u0
         wl_e = W.fisher3d(precision="fp64", n=args.n, nsteps=args.exact_steps)
-        u_e, sec_e, _, _ = timed_run(etd, torch, W.Workload(wl_e.name, wl_e.problem.replace(pade=0), wl_e.nsteps,
-                                                            wl_e.init, wl_e.seed), "fp64", args.exact_steps, 2)
-        u_p, _, _, _ = timed_run(etd, torch, wl_e, "fp64", args.exact_steps, 0)
+        u_e, sec_e, _, _, _ = timed_run(etd, torch, W.Workload(wl_e.name, wl_e.problem.replace(pade=0), wl_e.nsteps,
+                                                               wl_e.init, wl_e.seed), "fp64", args.exact_steps, 2, 3)
+        u_p, _, _, _, _ = timed_run(etd, torch, wl_e, "fp64", args.exact_steps, 0, 1)
         out["exact_exponential"] = {"ms_per_step": 1e3 * sec_e / args.exact_steps,
                                     "value": npts * args.exact_steps / sec_e, "steps": args.exact_steps,
                                     "rel_l2_vs_pade02": float((u_e - u_p).norm() / u_p.norm())}
@@ -362,22 +452,7 @@ def main():
         out["fhn2d"] = fhn2d_leg(etd, torch, W, args.fhn2d_steps)
 
     if not args.no_cpu_baseline:
-        # the oracle as it stands, in chunks of --cpu-steps steps until about
-        # --cpu-seconds of host time have been spent (bounded sample)
-        import oracle
-        p = wl.problem.replace(precision="fp64")
-        u = wl.u0()
-        cores = oracle.threads(0)
-        done, cs = 0, 0.0
-        while cs < args.cpu_seconds and done < 400:
-            t0 = time.perf_counter()
-            u = oracle.advance(p, u, args.cpu_steps, t0=done * p.tau, nthreads=0)
-            cs += time.perf_counter() - t0
-            done += args.cpu_steps
-        out["cpu_baseline"] = {"value": npts * done / cs, "unit": "grid-point updates/s", "cores": cores,
-                               "kind": "oracle",
-                               "sample": f"first {done} steps of {wl.name} from the same u0 in {cs:.1f} s "
-                                         f"(FP64 complex Thomas line solves, OpenMP over lines)"}
+        out["cpu_baseline"] = cpu_baseline(wl, args)
     print(json.dumps(out), flush=True)
 
 

@@ -130,12 +130,23 @@ TileShape default_x_shape(int NP, long nlines) {
     return TileShape{rows_per_wave(NP), 1};
 }
 
-// Defaults per matrix-core policy: split-BF16 products add four row blocks per
-// wave on two column blocks in the outer stages (each split B fragment then
-// feeds 24 MFMAs; 7-9% faster than (2, 2) on the 255^3 workload).
+// Defaults per matrix-core policy, measured on the 255^3 workload with the
+// autotuner:
+//  - split-BF16 products on an FP32 state take four row blocks per wave on
+//    two column or line blocks (each split B fragment then feeds 24 MFMAs;
+//    x stage 0.641 -> 0.570 ms per step against (2, 4));
+//  - on an FP64 state, split-BF16 products take (2, 1) in every stage (1.068
+//    -> 0.812 ms against the FP64 shapes) and FP32 products (2, 1) in the
+//    outer stages and (2, 2) in the x stage (1.254 -> 1.166 ms).
+template <typename M>
+constexpr bool fp64_state_reduced() {
+    return sizeof(typename M::elem) == 8 && sizeof(typename M::acc) == 4;
+}
+
 template <typename M, int NC>
 TileShape default_outer_for(int NP, long ncols16) {
     typedef typename M::elem T;
+    if (fp64_state_reduced<M>() && outer_shape_ok<T, NC>(NP, TileShape{2, 1})) return TileShape{2, 1};
     if (M::SPLIT_B && NC == 1 && outer_shape_ok<T, NC>(NP, TileShape{4, 2})) return TileShape{4, 2};
     // FP32 products at NP = 256 with at least 1024 two-block tiles take four
     // row blocks as well (2.4% faster on the 255^3 workload; with few tiles,
@@ -147,7 +158,14 @@ TileShape default_outer_for(int NP, long ncols16) {
 
 template <typename M, int NC>
 TileShape default_x_for(int NP, long nlines) {
-    return default_x_shape<typename M::elem, NC>(NP, nlines);
+    typedef typename M::elem T;
+    if (fp64_state_reduced<M>()) {
+        if (!M::SPLIT_B && x_shape_ok<T, NC>(NP, nlines, TileShape{2, 2})) return TileShape{2, 2};
+        if (x_shape_ok<T, NC>(NP, nlines, TileShape{2, 1})) return TileShape{2, 1};
+    }
+    if (M::SPLIT_B && sizeof(T) == 4 && NC == 1 && x_shape_ok<T, NC>(NP, nlines, TileShape{4, 2}))
+        return TileShape{4, 2};
+    return default_x_shape<T, NC>(NP, nlines);
 }
 
 int tile_threads(int NP) { return shape_threads(NP, rows_per_wave(NP)); }

@@ -87,6 +87,49 @@ __device__ __forceinline__ void gemm(const void* __restrict__ P, int NP, int rb0
     }
 }
 
+// The same K-loop over K blocks kb_lo .. kb_hi - 1 of a B operand that is
+// streamed through LDS in chunks of CKB K blocks: at_chunk(c) runs
+// (uniformly across the workgroup) before the first K block of the range's
+// chunk c and must leave that chunk readable by bload.  The A ring runs on
+// across chunk boundaries, so P keeps arriving PF K blocks ahead while a
+// chunk is exchanged.
+template <typename M, int RB, int NQ, int PF, int CKB, typename BL, typename CH>
+__device__ __forceinline__ void gemm_chunked(const void* __restrict__ P, int NP, int kb_lo, int kb_hi, int rb0,
+                                             int li, int lg, vec_t<typename M::acc, 4> (&acc)[RB][NQ], BL bload,
+                                             CH at_chunk) {
+    const long kstep = M::a_kstep(NP);
+    long off[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) off[r] = M::a_off(NP, rb0 + r, li, lg);
+    typename M::A ring[PF][RB];
+#pragma unroll
+    for (int i = 0; i < PF; ++i)
+#pragma unroll
+        for (int r = 0; r < RB; ++r) ring[i][r] = M::load_a(P, NP, off[r] + min(kb_lo + i, kb_hi - 1) * kstep);
+    for (int kb0 = kb_lo; kb0 < kb_hi; kb0 += PF) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int kb = kb0 + i;
+            if (kb >= kb_hi) break;
+            if ((kb - kb_lo) % CKB == 0) at_chunk((kb - kb_lo) / CKB);
+            typename M::A a_cur[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) a_cur[r] = ring[i][r];
+            const long kn = min(kb + PF, kb_hi - 1) * kstep;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) ring[i][r] = M::load_a(P, NP, off[r] + kn);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const typename M::B b = M::prep(bload(q, kb * M::KB + M::KL * lg));
+#pragma unroll
+                for (int t = 0; t < M::NSUB; ++t)
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) M::step(acc[r][q], a_cur[r], b, t);
+            }
+        }
+    }
+}
+
 template <typename T, int RB, int NQ>
 __device__ __forceinline__ void zero(typename Vec4<T>::type (&acc)[RB][NQ]) {
 #pragma unroll

@@ -550,33 +550,35 @@ StepArgs step_args(const Plan& pl, char* ws, const void* const Pdir[3]) {
 
 // One product-parallel launch: row groups of 16*NW rows x 16-column tiles,
 // as a one-dimensional grid (split_block maps it XCD by XCD).
-template <typename M, int NC, int KIND, int NW, int QP>
+template <typename M, int NC, int KIND, int NW, int BK, int KS>
 etd_status launch_split_k(const SplitArgs& a, long ncols, hipStream_t s) {
     typedef typename M::elem T;
-    const size_t lds = size_t(QP) * 16 * (a.NP + 16 / sizeof(T)) * sizeof(T);
-    auto k = split_product<M, NC, KIND, NW, QP>;
+    if (a.NP % (BK * KS) != 0) return fail(ETD_EINVAL, "2-D product chunks do not divide the padded extent");
+    const size_t lds = split_lds_bytes(SplitShape<KIND, NC>::NARR, BK, KS, sizeof(T));
+    auto k = split_product<M, NC, KIND, NW, BK, KS>;
     static size_t done = 0;
     HIP_TRY(set_lds(k, lds, done), "2-D product LDS attribute");
-    hipLaunchKernelGGL(k, dim3(unsigned(a.NP / (16 * NW) * (ncols / 16))), dim3(64 * NW), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(unsigned(a.NP / (16 * NW) * (ncols / 16))), dim3(64 * NW * KS), lds, s, a);
     HIP_TRY(hipGetLastError(), "2-D product launch");
     return ETD_OK;
 }
 
+// Chunks of 64 contracted indices with an FP64 state and 128 with an FP32
+// one (halved until they divide the padded extent, a multiple of 32), and
+// the contraction in two parts where both divide it.
 template <typename M, int NC, int KIND, int NW>
-etd_status launch_split_nw(const SplitArgs& a, long ncols, hipStream_t s) {
+etd_status launch_split_bk(const SplitArgs& a, long ncols, hipStream_t s) {
     typedef typename M::elem T;
-    constexpr int NARR = (KIND <= kSplitX1) ? 2 * NC : NC;
-    const size_t per = size_t(16) * (a.NP + 16 / sizeof(T)) * sizeof(T);
-    if constexpr (NARR % 4 == 0)
-        if (4 * per <= kMaxLds) return launch_split_k<M, NC, KIND, NW, 4>(a, ncols, s);
-    if constexpr (NARR % 2 == 0)
-        if (2 * per <= kMaxLds) return launch_split_k<M, NC, KIND, NW, 2>(a, ncols, s);
-    return launch_split_k<M, NC, KIND, NW, 1>(a, ncols, s);
+    if constexpr (sizeof(T) == 4)
+        if (a.NP % 256 == 0) return launch_split_k<M, NC, KIND, NW, 128, 2>(a, ncols, s);
+    if (a.NP % 128 == 0) return launch_split_k<M, NC, KIND, NW, 64, 2>(a, ncols, s);
+    if (a.NP % 64 == 0) return launch_split_k<M, NC, KIND, NW, 32, 2>(a, ncols, s);
+    return launch_split_k<M, NC, KIND, NW, 32, 1>(a, ncols, s);
 }
 
 template <typename M, int NC, int KIND>
 etd_status launch_split(const SplitArgs& a, long ncols, hipStream_t s) {
-    return a.NP % 64 == 0 ? launch_split_nw<M, NC, KIND, 4>(a, ncols, s) : launch_split_nw<M, NC, KIND, 2>(a, ncols, s);
+    return a.NP % 64 == 0 ? launch_split_bk<M, NC, KIND, 4>(a, ncols, s) : launch_split_bk<M, NC, KIND, 2>(a, ncols, s);
 }
 
 // 2-D problems take the product-parallel path when it has at least 128

@@ -552,28 +552,54 @@ __device__ __forceinline__ void split_block(int nrg, int T, int L, int& rg, int&
     ct = t / nrg;
 }
 
-// QP arrays are staged per pass (as many as the LDS holds), so each P
-// fragment feeds QP MFMAs per step.
-template <typename M, int NC, int KIND, int NW, int QP>
-__global__ __launch_bounds__(64 * NW) void split_product(SplitArgs a) {
+// Every array of the launch is staged at once, K chunk by K chunk: the B
+// panel (16 columns x NP contracted indices per array) streams through two
+// LDS buffers of BK indices, the next chunk's loads in flight (in registers)
+// while the matrix cores work on the current one.  Each P fragment feeds
+// NARR MFMAs per step.  The contraction is split in KS parts over as many
+// wave groups (each its own buffers), so a SIMD holds KS waves whose loads
+// and MFMAs interleave; the parts are summed in LDS, in a fixed order, and
+// the first group runs the epilogue.
+template <int KIND, int NC>
+struct SplitShape {
+    static constexpr int NARR = (KIND <= kSplitX1) ? 2 * NC : NC;   // B arrays of the product
+    // arrays read from memory to form them (YF forms f(U) from U while staging)
+    static constexpr int NRAW = (KIND == kSplitYF) ? NC : NARR;
+};
+
+// LDS of a launch: KS x two buffers of narr arrays x 16 columns x (bk + pad)
+inline size_t split_lds_bytes(int narr, int bk, int ks, size_t elem) {
+    return size_t(ks) * 2 * size_t(narr) * 16 * (bk + 16 / elem) * elem;
+}
+
+// BK contracted indices per chunk; KS * BK divides the padded extent NP, so
+// every chunk is whole and inside the field.
+template <typename M, int NC, int KIND, int NW, int BK, int KS>
+__global__ __launch_bounds__(64 * NW * KS) void split_product(SplitArgs a) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
     typedef typename M::acc AT;                 // accumulator type of the products
     typedef typename Vec4<AT>::type A4;
     constexpr bool YK = KIND <= kSplitYB;   // contracted direction y, columns are x
-    constexpr int NARR = (KIND <= kSplitX1) ? 2 * NC : NC;
-    static_assert(NARR % QP == 0, "passes must cover the arrays");
+    constexpr int NARR = SplitShape<KIND, NC>::NARR;
+    constexpr int NRAW = SplitShape<KIND, NC>::NRAW;
+    static_assert(BK % M::KB == 0, "chunks hold whole K blocks");
+    constexpr int RSK = BK + 16 / int(sizeof(T));   // LDS stride between columns
+    constexpr int AST = 16 * RSK;                   // between arrays
+    constexpr int BST = NARR * AST;                 // between the two buffers of a part
+    constexpr int GT = 64 * NW;                     // threads of one part's wave group
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* X = reinterpret_cast<T*>(smem_raw);
     const int NP = a.NP;
-    const int RS = NP + 16 / int(sizeof(T));
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int kh = w / NW;                          // contraction part of this wave
+    const int ptid = tid - kh * GT;                 // thread index within the part
     const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
     int rg, ct;
     split_block(a.NP / (16 * NW), int(gridDim.x), int(blockIdx.x), rg, ct);
-    const int rb0 = rg * NW + w;   // this wave's 16-row block
+    const int rb0 = rg * NW + (w - kh * NW);   // this wave's 16-row block
     const int col0 = ct * 16;
     const long sc = a.sc;
     T* U = static_cast<T*>(a.U);
@@ -590,100 +616,126 @@ __global__ __launch_bounds__(64 * NW) void split_product(SplitArgs a) {
         y = YK ? k : col0 + c;
     };
 
-    const int AST = 16 * RS;
     // Staging moves 16-byte chunks of VN elements: VN consecutive columns of
     // one contracted index k (y kinds, x contiguous) or VN consecutive k of
     // one line (x kinds).  Every padded extent is a multiple of VN and every
     // field is 256-byte aligned, so each chunk is one aligned vector load.
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
-    constexpr int UNR = 8;   // chunks per array in flight per thread
-    const int nchunk = 16 * NP / VN;
-    auto chunk = [&](int v, int& k, int& c) {
+    constexpr int NV = 16 * BK / VN;                // vectors per array and K chunk
+    constexpr int PER = (NV + GT - 1) / GT;         // per thread
+    auto vec_at = [&](int v, int& k, int& c) {      // vector v of a chunk -> (k within it, column)
         if constexpr (YK) {
             k = v / (16 / VN);
             c = (v % (16 / VN)) * VN;
         } else {
-            c = v / (NP / VN);
-            k = (v % (NP / VN)) * VN;
+            c = v / (BK / VN);
+            k = (v % (BK / VN)) * VN;
         }
     };
-    auto vload = [&](const T* base, long gi) { return *reinterpret_cast<const TV*>(base + gi); };
-    // chunk of array q at (k, c)
-    auto fetch = [&](int q, int k, int c) -> TV {
-        const long gi = at(k, c);
-        if constexpr (KIND == kSplitYF) {
-            if (q < NC) return vload(U, gi + q * sc);
-            TV u[NC];
+    auto raw_ptr = [&](int q) -> const T* {
+        if constexpr (KIND == kSplitYF) return U + q * sc;
+        else if constexpr (KIND == kSplitYB) return q < NC ? WC + q * sc : WD + (q - NC) * sc;
+        else if constexpr (KIND == kSplitX1) return q < NC ? WA + q * sc : WB + (q - NC) * sc;
+        else if constexpr (KIND == kSplitX3) return WD + q * sc;
+        else return WC + q * sc;
+    };
+    const int nch = NP / (BK * KS);                 // chunks per part
+    const int kbase = kh * nch * BK;                // first contracted index of this part
+    T* const mybuf = X + kh * 2 * BST;
+    TV pre[PER][NRAW];
+    auto load_chunk = [&](int ch) {
 #pragma unroll
-            for (int cc = 0; cc < NC; ++cc) u[cc] = vload(U, gi + cc * sc);
-            TV r;
+        for (int j = 0; j < PER; ++j) {
+            const int v = ptid + j * GT;
+            if (NV % GT == 0 || v < NV) {
+                int k, c;
+                vec_at(v, k, c);
+                const long gi = at(kbase + ch * BK + k, c);
 #pragma unroll
-            for (int j = 0; j < VN; ++j) {
-                T uj[NC], f[NC];
-#pragma unroll
-                for (int cc = 0; cc < NC; ++cc) uj[cc] = u[cc][j];
-                int x, y;
-                coords(k, c + j, x, y);
-                react<T, NC>(a.rxn, uj, f, x, y, 0);
-                r[j] = f[q - NC];
+                for (int q = 0; q < NRAW; ++q) pre[j][q] = *reinterpret_cast<const TV*>(raw_ptr(q) + gi);
             }
-            return r;
-        } else if constexpr (KIND == kSplitYB) {
-            return q < NC ? vload(WC, gi + q * sc) : vload(WD, gi + (q - NC) * sc);
-        } else if constexpr (KIND == kSplitX1) {
-            return q < NC ? vload(WA, gi + q * sc) : vload(WB, gi + (q - NC) * sc);
-        } else if constexpr (KIND == kSplitX2 || KIND == kSplitX4) {
-            return vload(WC, gi + q * sc);
-        } else {
-            return vload(WD, gi + q * sc);
         }
     };
-    A4 acc[NARR / QP][1][QP];
+    auto store_chunk = [&](int ch) {
+        T* buf = mybuf + (ch & 1) * BST;
 #pragma unroll
-    for (int q0 = 0; q0 < NARR; q0 += QP) {
-        // stage arrays q0 .. q0+QP-1 of the tile: X[array][column][k]; all
-        // loads of a round are issued before its LDS stores
-        for (int v0 = tid; v0 < nchunk; v0 += UNR * int(blockDim.x)) {
-            TV val[QP][UNR];
+        for (int j = 0; j < PER; ++j) {
+            const int v = ptid + j * GT;
+            if (NV % GT == 0 || v < NV) {
+                int k, c;
+                vec_at(v, k, c);
+                TV val[NARR];
 #pragma unroll
-            for (int j = 0; j < UNR; ++j) {
-                const int v = v0 + j * int(blockDim.x);
-                if (v < nchunk) {
-                    int k, c;
-                    chunk(v, k, c);
+                for (int q = 0; q < NRAW; ++q) val[q] = pre[j][q];
+                if constexpr (KIND == kSplitYF) {
 #pragma unroll
-                    for (int q = 0; q < QP; ++q) val[q][j] = fetch(q0 + q, k, c);
+                    for (int e = 0; e < VN; ++e) {
+                        T uj[NC], f[NC];
+#pragma unroll
+                        for (int cc = 0; cc < NC; ++cc) uj[cc] = pre[j][cc][e];
+                        int x, y;
+                        coords(kbase + ch * BK + k, c + e, x, y);
+                        react<T, NC>(a.rxn, uj, f, x, y, 0);
+#pragma unroll
+                        for (int cc = 0; cc < NC; ++cc) val[NC + cc][e] = f[cc];
+                    }
                 }
-            }
 #pragma unroll
-            for (int j = 0; j < UNR; ++j) {
-                const int v = v0 + j * int(blockDim.x);
-                if (v < nchunk) {
-                    int k, c;
-                    chunk(v, k, c);
+                for (int q = 0; q < NARR; ++q) {
+                    T* dst = buf + q * AST + c * RSK + k;
+                    if constexpr (YK) {
 #pragma unroll
-                    for (int q = 0; q < QP; ++q) {
-                        T* dst = X + q * AST + c * RS + k;
-                        if constexpr (YK) {
-#pragma unroll
-                            for (int e = 0; e < VN; ++e) dst[e * RS] = val[q][j][e];
-                        } else {
-                            *reinterpret_cast<TV*>(dst) = val[q][j];
-                        }
+                        for (int e = 0; e < VN; ++e) dst[e * RSK] = val[q][e];
+                    } else {
+                        *reinterpret_cast<TV*>(dst) = val[q];
                     }
                 }
             }
         }
+    };
+    load_chunk(0);
+    store_chunk(0);
+    if (nch > 1) load_chunk(1);
+    A4 acc[1][NARR];
+    zero<AT, 1, NARR>(acc);
+    const int nkbp = nch * (BK / M::KB);            // K blocks per part
+    // P fragments are requested four K blocks ahead
+    gemm_chunked<M, 1, NARR, 4, BK / M::KB>(
+        a.P, NP, kh * nkbp, (kh + 1) * nkbp, rb0, li, lg, acc,
+        [&](int q, int k0) {
+            const int ch = (k0 - kbase) / BK;
+            return lds_vec<T, M::KL>(mybuf + (ch & 1) * BST + q * AST + li * RSK + (k0 - kbase - ch * BK));
+        },
+        [&](int ch) {
+            __syncthreads();   // chunk ch is in LDS; chunk ch - 1's buffer is free
+            if (ch + 1 < nch) store_chunk(ch + 1);
+            if (ch + 2 < nch) load_chunk(ch + 2);
+        });
+    if constexpr (KS > 1) {
+        // sum the parts in order: part p > 0 leaves its accumulators in LDS
+        // (lane-major), part 0 adds them and runs the epilogue
         __syncthreads();
-        zero<AT, 1, QP>(acc[q0 / QP]);
-        // one wave per SIMD: P fragments are requested four K blocks ahead
-        gemm<M, 1, QP, 4>(a.P, NP, rb0, li, lg, acc[q0 / QP],
-                       [&](int qq, int k0) { return lds_vec<T, M::KL>(X + qq * AST + li * RS + k0); });
+        AT* red = reinterpret_cast<AT*>(smem_raw);
+        const int wr = w - kh * NW;
+        if (kh > 0) {
+#pragma unroll
+            for (int q = 0; q < NARR; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    red[(((kh - 1) * NW + wr) * NARR * 4 + q * 4 + e) * 64 + lane] = acc[0][q][e];
+        }
         __syncthreads();
+        if (kh > 0) return;
+#pragma unroll
+        for (int p = 1; p < KS; ++p)
+#pragma unroll
+            for (int q = 0; q < NARR; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[0][q][e] += red[(((p - 1) * NW + wr) * NARR * 4 + q * 4 + e) * 64 + lane];
     }
     // result of array q at register e
-    auto res = [&](int q, int e) { return acc[q / QP][0][q % QP][e]; };
+    auto res = [&](int q, int e) { return acc[0][q][e]; };
 
     const T* __restrict__ dg = static_cast<const T*>(a.diag);
     const T tau = T(a.tau);

@@ -249,9 +249,10 @@ def test_batched_workload_sampled_against_oracle(etd, oracle_mod):
 def test_product_parallel_2d_matches_fused_stages(etd, precision, reaction, n):
     """Large 2-D single plans run every mode product as a launch of its own;
     a batch of the same single problem runs the fused stage kernels.  Both
-    compute every output with the same operations in the same order, up to
-    the compiler's fusing of a few multiply-adds: FP64 results are bitwise
-    equal, FP32 ones within 1e-6."""
+    compute every output with the same operations, except that the
+    product-parallel launches split each contraction in two halves summed at
+    the end (and the compiler fuses a few epilogue multiply-adds): FP64
+    results agree to a few units in the last place, FP32 ones within 1e-6."""
     kw = dict(kappa=(1e-3, 1e-4)) if reaction == "fhn_cubic" else dict(kappa=(0.01,), q=0.3)
     p = W.Problem(dim=2, n=n, tau=0.02, reaction=reaction, precision=precision, **kw)
     u0 = W.u0_fhn_patch(p, 3, patch=0.3) if reaction == "fhn_cubic" else W.u0_sine_noise(p, 3)
@@ -265,7 +266,7 @@ def test_product_parallel_2d_matches_fused_stages(etd, precision, reaction, n):
     b.close()
     diff = np.abs(single - fused).max() / np.abs(fused).max()
     print(f"  max rel diff {diff:.2e}")
-    assert diff <= (0.0 if precision == "fp64" else 1e-6) or np.array_equal(single, fused)
+    assert diff <= (1e-14 if precision == "fp64" else 1e-6)
 
 
 def test_independent_plans_and_a_batch_on_concurrent_streams(etd):

@@ -311,3 +311,134 @@ def test_independent_plans_and_a_batch_on_concurrent_streams(etd):
     for got, want in zip(z, ref[2]):
         assert np.array_equal(host(got), want)
     a.close(), b.close(), c.close()
+
+
+# ---------------------------------------------------------------------------
+# the flow schedule: one persistent dataflow launch per step (disabled)
+#
+# A batch schedule that ran every stage and shape group of a step in ONE
+# persistent launch (workgroups taking tiles from a queue; a tile of a later
+# stage polling per-instance counters of finished tiles of the stage before)
+# did not complete on the GPU: the one-instance 63^2 case below ran past
+# 180 s without output, twice (the second time with counter polls that no
+# longer invalidate the L2).  The cause is not established, so the schedule
+# is not in the library; these tests stay, skipped, for a version whose
+# cross-workgroup synchronisation is shown to work.
+# ---------------------------------------------------------------------------
+
+FLOW_SKIP = pytest.mark.skip(reason="flow schedule removed: its first runs did not complete (cross-workgroup "
+                                    "counter waits never saw the producers' counts; cause not established)")
+
+@FLOW_SKIP
+def test_flow_schedule_matches_grouped_launches(etd, oracle_mod):
+    """Uneven 2-D FP32 instances (n in {127, 255, 511, 1023}) in one launch per
+    call: bit-identical to the grouped per-stage launches (tile shapes change
+    no output's arithmetic), and the first instance of each extent against
+    the FP64 oracle."""
+    probs, u0s, _ = W.batched2d(count=24, nsteps=7)
+    b = etd.Batch(probs)
+    f = b.fields(u0s)
+    b.advance(f, 7, t0=0.05)
+    ref = [host(x) for x in f]
+    b.set_schedule("flow")
+    print(f"  flow tiles {[b.tiles(i)[:2] for i in range(4)]}")
+    f = b.fields(u0s)
+    b.advance(f, 7, t0=0.05)
+    seen = set()
+    for i, p in enumerate(probs):
+        got = host(f[i])
+        assert np.array_equal(got, ref[i]), i
+        if p.n[0] not in seen:
+            seen.add(p.n[0])
+            err = rel_l2(got, oracle_mod.advance(p, u0s[i], 7, t0=0.05))
+            print(f"  instance {i} n={p.n[0]}: rel_l2 {err:.2e}")
+            assert err <= FP32_TOL
+    # back to the grouped schedule: same results again
+    b.set_schedule("groups")
+    f = b.fields(u0s)
+    b.advance(f, 7, t0=0.05)
+    for i in range(len(probs)):
+        assert np.array_equal(host(f[i]), ref[i]), i
+    b.close()
+
+
+@FLOW_SKIP
+@pytest.mark.parametrize("case", [
+    ("3d-fhn-fp64", [dict(dim=3, n=(63, 127, 63), kappa=(1e-3, 1e-4), tau=0.02, reaction="fhn_cubic"),
+                     dict(dim=3, n=(60, 100, 50), kappa=(2e-3, 3e-4), tau=0.01, reaction="fhn_cubic")]),
+    ("3d-mms-fp64", [dict(dim=3, n=(63, 60, 33), kappa=(0.1,), q=0.2, tau=0.01, reaction="ac_mms",
+                          rxn_param=(1.0, 0.0))]),
+    ("2d-fisher-fp64_bf16x6", [dict(dim=2, n=(255, 127), kappa=(0.01,), q=0.3, tau=0.01, reaction="fisher",
+                                    precision="fp64_bf16x6"),
+                               dict(dim=2, n=(127, 255), kappa=(0.02,), q=0.1, tau=0.02, reaction="saturating",
+                                    precision="fp64_bf16x6")]),
+], ids=lambda c: c[0])
+def test_flow_schedule_3d_systems_and_time_dependent(etd, oracle_mod, case):
+    """3-D two-component, time-dependent forcing and FP64-state reduced-product
+    batches in the flow schedule against the oracle, over several steps so
+    that every stage waits on the one before it."""
+    name, kws = case
+    probs = [W.Problem(**kw) for kw in kws]
+    b = etd.Batch(probs)
+    b.set_schedule("flow")
+    u0s = [W.u0_fhn_patch(p, 40 + i, patch=0.4) if p.ncomp == 2 else
+           (W.initial_field(p, "sine", 0) * np.exp(-0.3) if p.reaction == "ac_mms" else
+            0.5 * W.u0_sine_noise(p, 40 + i)) for i, p in enumerate(probs)]
+    f = b.fields(u0s)
+    b.advance(f, 9, t0=0.3)
+    tol = FP64_TOL if probs[0].precision == "fp64" else FP32_TOL
+    for i, p in enumerate(probs):
+        err = rel_l2(host(f[i]), oracle_mod.advance(p.replace(precision="fp64"), u0s[i], 9, t0=0.3))
+        print(f"  {name} instance {i} n={p.n}: rel_l2 {err:.2e}")
+        assert err <= tol, i
+    b.close()
+
+
+@FLOW_SKIP
+def test_flow_schedule_small_grid_latency_path(etd, oracle_mod):
+    """The 63^2 Fisher-KPP workload as a one-instance batch in the flow
+    schedule: all 100 steps in one launch, four-wave tiles; bit-identical to
+    the single plan and within 1e-12 of the oracle; replayed from a graph."""
+    import torch
+    wl = W.fisher2d_small()
+    p = wl.problem
+    b = etd.Batch([p])
+    b.set_schedule("flow")
+    f = b.fields([wl.u0()])
+    b.advance(f, wl.nsteps)
+    got = host(f[0])
+    st = etd.Stepper(p)
+    single = host(st.advance(st.field(wl.u0()), wl.nsteps))
+    st.close()
+    err = rel_l2(got, oracle_mod.advance(p, wl.u0(), wl.nsteps))
+    print(f"  rel_l2 vs oracle {err:.2e}; tiles {b.tiles(0)[:4]}")
+    assert err <= FP64_TOL
+    assert np.array_equal(got, single)
+    s = torch.cuda.Stream()
+    g_f = b.fields([wl.u0()])
+    torch.cuda.synchronize()
+    g = b.capture(g_f, wl.nsteps, s)
+    for r in range(3):
+        for x in g_f:
+            x.copy_(torch.as_tensor(wl.u0().reshape(p.shape), device=x.device))
+        torch.cuda.synchronize()
+        g.launch(s)
+        s.synchronize()
+        assert np.array_equal(host(g_f[0]), got), r
+    g.close()
+    b.close()
+
+
+@FLOW_SKIP
+def test_flow_schedule_refused_where_no_wave_count_fits(etd):
+    """Padded extents 32 and 96 fit no common W in {8, 4}; the batch keeps its
+    grouped schedule."""
+    probs = [W.Problem(dim=2, n=(31, 95), kappa=(0.01,), tau=0.01, reaction="fisher")]
+    b = etd.Batch(probs)
+    with pytest.raises(etd.EtdError) as ei:
+        b.set_schedule("flow")
+    assert ei.value.status == etd.ETD_EUNSUPPORTED
+    f = b.fields([W.u0_sine_noise(probs[0], 1)])
+    b.advance(f, 2)
+    assert np.isfinite(host(f[0])).all()
+    b.close()

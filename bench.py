@@ -29,6 +29,7 @@ import json
 import math
 import os
 import re
+import statistics
 import sys
 import time
 
@@ -244,11 +245,14 @@ def batched_leg(etd, torch, W, nsteps):
     return out
 
 
-def latency_leg(etd, torch, W, nsteps):
-    """The 63^2 Fisher-KPP case, where a step is a few microseconds of work:
-    eager etd_advance calls of one step each vs one captured graph."""
+def latency_leg(etd, torch, W, nsteps, repeats=5):
+    """The 63^2 Fisher-KPP case, where a step is 4.5 MFLOP: per-stage launches
+    as eager one-step calls and as one captured graph of the run, and the
+    resident schedule (every step of a call in one cooperative launch) as
+    one-step calls and as one call of the whole run (median of `repeats`)."""
     wl = W.fisher2d_small()
     st = etd.Stepper(wl.problem)
+    st.set_schedule("stages")
     u = st.field(wl.u0())
     st.advance(u, 2)
     torch.cuda.synchronize()
@@ -266,9 +270,27 @@ def latency_leg(etd, torch, W, nsteps):
     s.synchronize()
     graph = time.perf_counter() - t0
     g.close()
+    st.set_schedule("resident")
+    st.advance(u, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        st.advance(u, 1)
+    torch.cuda.synchronize()
+    res_calls = time.perf_counter() - t0
+    runs = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.advance(u, nsteps)
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t0)
     st.close()
     return {"workload": wl.name, "steps": nsteps, "eager_us_per_step": 1e6 * eager / nsteps,
-            "graph_us_per_step": 1e6 * graph / nsteps}
+            "graph_us_per_step": 1e6 * graph / nsteps,
+            "resident_one_step_calls_us_per_step": 1e6 * res_calls / nsteps,
+            "resident_us_per_step": 1e6 * statistics.median(runs) / nsteps,
+            "resident_us_per_step_runs": [1e6 * r / nsteps for r in runs]}
 
 
 def fhn2d_leg(etd, torch, W, nsteps, repeats=5):

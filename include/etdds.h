@@ -215,6 +215,31 @@ etd_status etd_plan_tiles(const etd_plan* plan, int tiles[6]);
 etd_status etd_plan_set_tiles(etd_plan* plan, const int tiles[6]);
 etd_status etd_plan_autotune(etd_plan* plan, void* workspace_dev, void* stream);
 
+/* How etd_advance launches the stages of Algorithm 2 (speed only: shapes and
+ * schedules give identical results, except that the manufactured Allen-Cahn
+ * source's time factor e^{-lambda t} is formed on the device by the resident
+ * schedule and on the host otherwise, which may differ in the last bit).
+ *  - ETD_SCHEDULE_STAGES: one launch per stage and step (two-dimensional grids
+ *    with at least 128 blocks of 64 y rows x 16 x columns run every mode
+ *    product as a launch of its own).
+ *  - ETD_SCHEDULE_RESIDENT: all steps of the call in ONE cooperative launch
+ *    whose workgroups run the stages' tiles in turn, with a grid-wide barrier
+ *    between stages.  Applies to grids whose directions share one padded
+ *    extent of at most 128 points.  etd_advance returns ETD_EUNSUPPORTED on a
+ *    stream that is capturing a graph; stage timing records nothing for it.
+ *  - ETD_SCHEDULE_AUTO (default): RESIDENT where it applies and no stage has
+ *    more than 16 tiles of 16 columns or lines (two-dimensional grids up to
+ *    128 x 128 padded points), on a stream that is not capturing and with
+ *    stage timing off; STAGES otherwise.
+ * etd_plan_set_schedule: ETD_EINVAL for an unknown value, ETD_EUNSUPPORTED for
+ * RESIDENT on a plan it does not apply to (the plan is then unchanged).
+ * etd_plan_schedule: the schedule (STAGES or RESIDENT) that etd_advance takes
+ * on a stream that is not capturing, with stage timing off.  Tile shapes set
+ * with etd_plan_set_tiles apply to the STAGES schedule only. */
+typedef enum { ETD_SCHEDULE_AUTO = 0, ETD_SCHEDULE_STAGES = 1, ETD_SCHEDULE_RESIDENT = 2 } etd_schedule;
+etd_status etd_plan_set_schedule(etd_plan* plan, int schedule);
+etd_status etd_plan_schedule(const etd_plan* plan, int* schedule);
+
 /* Batches: `count` (1..4096) independent problems advanced together.  They
  * must share dim, ncomp and precision; extents, box, coefficients, time step,
  * reaction and Pade order are per instance.  Instances of one padded shape

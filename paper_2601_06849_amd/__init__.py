@@ -58,6 +58,7 @@ EXPORTS = ("etd_plan_create", "etd_plan_workspace_bytes", "etd_plan_upload", "et
            "etd_plan_problem", "etd_plan_table", "etd_timing_enable", "etd_timing_read",
            "etd_adjoint_workspace_bytes", "etd_adjoint",
            "etd_plan_tiles", "etd_plan_set_tiles", "etd_plan_autotune",
+           "etd_plan_set_schedule", "etd_plan_schedule",
            "etd_batch_create", "etd_batch_workspace_bytes", "etd_batch_upload", "etd_batch_advance",
            "etd_batch_autotune", "etd_batch_tiles", "etd_batch_groups", "etd_batch_destroy",
            "etd_graph_capture", "etd_batch_graph_capture", "etd_graph_launch", "etd_graph_destroy",
@@ -90,6 +91,8 @@ def lib():
             "etd_plan_tiles": [vp, ipp],
             "etd_plan_set_tiles": [vp, ipp],
             "etd_plan_autotune": [vp, vp, vp],
+            "etd_plan_set_schedule": [vp, ip],
+            "etd_plan_schedule": [vp, ipp],
             "etd_batch_create": [ctypes.POINTER(etd_problem), ip, ctypes.POINTER(vp)],
             "etd_batch_workspace_bytes": [vp, ctypes.POINTER(sz)],
             "etd_batch_upload": [vp, vp, sz, vp],
@@ -301,6 +304,22 @@ def etd_plan_set_tiles(plan, tiles):
     _check(lib().etd_plan_set_tiles(plan, (ctypes.c_int * 6)(*flat)))
 
 
+SCHEDULE = {"auto": 0, "stages": 1, "resident": 2}
+
+
+def etd_plan_set_schedule(plan, schedule):
+    """schedule: "auto", "stages" or "resident" (or its ETD_SCHEDULE_* value)."""
+    value = SCHEDULE[schedule] if isinstance(schedule, str) else int(schedule)
+    _check(lib().etd_plan_set_schedule(plan, value))
+
+
+def etd_plan_schedule(plan):
+    """"stages" or "resident": the schedule etd_advance takes outside capture, timing off."""
+    v = ctypes.c_int(-1)
+    _check(lib().etd_plan_schedule(plan, ctypes.byref(v)))
+    return {1: "stages", 2: "resident"}[v.value]
+
+
 def etd_plan_autotune(plan, workspace, stream=None):
     _check(lib().etd_plan_autotune(plan, _ptr(workspace), _stream(stream)))
 
@@ -443,6 +462,12 @@ class Stepper:
 
     def set_tiles(self, tiles):
         etd_plan_set_tiles(self.plan, tiles)
+
+    def set_schedule(self, schedule):
+        etd_plan_set_schedule(self.plan, schedule)
+
+    def schedule(self):
+        return etd_plan_schedule(self.plan)
 
     def capture(self, u, nsteps: int, stream, t0: float = 0.0):
         """Graph of advance(u, nsteps, t0) captured from `stream` (not the null stream)."""

@@ -282,6 +282,27 @@ etd_status etd_plan_set_tiles(etd_plan* plan, const int tiles[6]) {
     return ETD_OK;
 }
 
+etd_status etd_plan_set_schedule(etd_plan* plan, int schedule) {
+    if (!plan) return fail(ETD_EINVAL, "NULL plan");
+    if (schedule != ETD_SCHEDULE_AUTO && schedule != ETD_SCHEDULE_STAGES && schedule != ETD_SCHEDULE_RESIDENT)
+        return fail(ETD_EINVAL, "schedule must be ETD_SCHEDULE_AUTO, _STAGES or _RESIDENT");
+    if (schedule == ETD_SCHEDULE_RESIDENT && !resident_eligible(plan->p))
+        return fail(ETD_EUNSUPPORTED, "the resident schedule needs one padded extent of at most 128 in every direction");
+    plan->p.schedule = schedule;
+    return ETD_OK;
+}
+
+etd_status etd_plan_schedule(const etd_plan* plan, int* schedule) {
+    if (!plan || !schedule) return fail(ETD_EINVAL, "NULL argument");
+    const Plan& pl = plan->p;
+    int s = ETD_SCHEDULE_STAGES;
+    if (resident_eligible(pl) && (pl.schedule == ETD_SCHEDULE_RESIDENT ||
+                                  (pl.schedule == ETD_SCHEDULE_AUTO && resident_tiles(pl) <= kResidentAutoTiles)))
+        s = ETD_SCHEDULE_RESIDENT;
+    *schedule = s;
+    return ETD_OK;
+}
+
 // A batch offers no table query and uploads only the packed image, so the
 // FP64 host tables of its instances (an n_d x n_d matrix per direction) are
 // dropped once the image is built.

@@ -628,11 +628,103 @@ etd_status run_steps_split2d(const Plan& pl, StageTimer& tm, char* ws, double t0
     return ETD_OK;
 }
 
+// Resident schedule: every step of a run in one cooperative launch, for grids
+// whose directions share one padded extent of at most kResidentMaxNP points
+// (fused tiles of one row block per wave and one column or line block: NP/16
+// waves).  AUTO takes it when no stage has more than kResidentAutoTiles tiles,
+// outside graph capture and stage timing.  Measured per step (FP64 Fisher-KPP,
+// whole-run calls): 31^2 13.5 -> 10.7 us, 63^2 21.3 -> 15.1 us, 127^2 48.5 ->
+// 34.9 us; but 31^3 (64 tiles) 21.1 -> 35.6 us and 63^3 (256 tiles) 33.7 ->
+// 108 us, since the grid-wide barrier's cost grows with the workgroup count.
+constexpr int kResidentMaxNP = 128;
+constexpr int kResidentThreads = 512;
+constexpr long kResidentAutoTiles = 16;
+
+bool resident_eligible(const Plan& pl) {
+    const int NP = pl.np[0];
+    if (NP > kResidentMaxNP) return false;
+    for (int d = 1; d < pl.dim; ++d)
+        if (pl.np[d] != NP) return false;
+    return !use_split2d(pl);
+}
+
+// Tiles of the largest stage (one 16-column or 16-line block each).
+long resident_tiles(const Plan& pl) {
+    const long px = pl.np[0], py = pl.np[1], pz = pl.np[2];
+    long t = std::max(px / 16 * pz, py * pz / 16);   // y (middle or first) and x stages
+    if (pl.dim == 3) t = std::max(t, px * py / 16);    // z stage
+    return t;
+}
+
+bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus c = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &c) == hipSuccess && c != hipStreamCaptureStatusNone;
+}
+
+// The schedule a run takes: ETD_SCHEDULE_STAGES or ETD_SCHEDULE_RESIDENT, or
+// ETD_SCHEDULE_AUTO if a forced resident schedule cannot run here (capture).
+int resolve_schedule(const Plan& pl, const StageTimer& tm, hipStream_t s) {
+    if (pl.schedule == ETD_SCHEDULE_STAGES || !resident_eligible(pl)) return ETD_SCHEDULE_STAGES;
+    const bool capturing = stream_capturing(s);
+    if (pl.schedule == ETD_SCHEDULE_RESIDENT) return capturing ? ETD_SCHEDULE_AUTO : ETD_SCHEDULE_RESIDENT;
+    if (capturing || tm.on || resident_tiles(pl) > kResidentAutoTiles) return ETD_SCHEDULE_STAGES;
+    return ETD_SCHEDULE_RESIDENT;
+}
+
+template <typename M, int NC>
+etd_status run_steps_resident(const Plan& pl, char* ws, double t0, int nsteps, hipStream_t s) {
+    typedef typename M::elem T;
+    const void* Pdir[3] = {ws + pl.lay.P[0], ws + pl.lay.P[1], ws + pl.lay.P[2]};
+    const StepArgs st = step_args(pl, ws, Pdir);
+    ResidentArgs a{};
+    a.nouter = st.nouter;
+    long ntiles = st.nlines / 16;
+    for (int k = 0; k < st.nouter; ++k) {
+        a.outer[k] = st.outer[k];
+        a.outer[k].rxn = rxn_args(pl, ws, t0);   // the kernel sets each step's time
+        a.otiles[k] = st.ocols[k];
+        ntiles = std::max(ntiles, a.otiles[k]);
+    }
+    a.x = st.x;
+    a.x.rxn = rxn_args(pl, ws, t0);
+    a.xtiles = st.nlines / 16;
+    a.nsteps = nsteps;
+    a.t0 = t0;
+    const int NP = pl.np[0];
+    const size_t lds = std::max(outer_lds_bytes(NP, 2 * NC, 1, sizeof(T)), x_lds_bytes(NP, 2 * NC, 1, sizeof(T)));
+    const int thr = shape_threads(NP, 1);
+    auto k = resident_steps<M, NC, kResidentThreads>;
+    static size_t done = 0;
+    static GridCache gc;
+    static int coop = -1;
+    if (coop < 0) {
+        int dev = 0, c = 0;
+        HIP_TRY(hipGetDevice(&dev), "device query");
+        HIP_TRY(hipDeviceGetAttribute(&c, hipDeviceAttributeCooperativeLaunch, dev), "cooperative launch query");
+        coop = c;
+    }
+    if (!coop) return fail(ETD_EUNSUPPORTED, "the device does not support cooperative launches");
+    HIP_TRY(set_lds(k, lds, done), "resident schedule LDS attribute");
+    const long grid = gc.grid(k, thr, lds, ntiles);
+    if (gc.resident < 1) return fail(ETD_EHIP, "resident schedule: occupancy query failed");
+    void* args[] = {&a};
+    HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k), dim3(unsigned(grid)), dim3(thr), args,
+                                       unsigned(lds), s),
+            "resident schedule launch");
+    return ETD_OK;
+}
+
 template <typename M, int NC>
 etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int nsteps, hipStream_t s,
                      typename M::elem* w_out = nullptr) {
     typedef typename M::elem T;
     if (w_out == nullptr && use_split2d(pl)) return run_steps_split2d<M, NC>(pl, tm, ws, t0, nsteps, s);
+    if (w_out == nullptr) {
+        const int sch = resolve_schedule(pl, tm, s);
+        if (sch == ETD_SCHEDULE_AUTO)
+            return fail(ETD_EUNSUPPORTED, "the resident schedule is one cooperative launch and cannot be captured");
+        if (sch == ETD_SCHEDULE_RESIDENT) return run_steps_resident<M, NC>(pl, ws, t0, nsteps, s);
+    }
     const void* Pdir[3] = {ws + pl.lay.P[0], ws + pl.lay.P[1], ws + pl.lay.P[2]};
     StepArgs a = step_args(pl, ws, Pdir);
     a.x.Wout = w_out;

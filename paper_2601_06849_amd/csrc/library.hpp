@@ -8,6 +8,7 @@
 // instantiated only where a unit uses them (kern_<precision>.hip).
 #pragma once
 
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -105,6 +105,7 @@ struct Plan {
     // 0 = the built-in default, else set by the autotuner or the caller
     int tile_rb[3] = {0, 0, 0};
     int tile_cb[3] = {0, 0, 0};
+    int schedule = 0;                       // etd_schedule of etd_advance (0: AUTO)
 };
 
 etd_status build_plan(const etd_problem& p, Plan& out, std::string& err);

@@ -872,6 +872,51 @@ __global__ __launch_bounds__(MAXT) void x_group(Group<XArgs> g) {
 }
 
 // ---------------------------------------------------------------------------
+// Resident schedule for small grids: every step of a run in ONE cooperative
+// launch.  Each stage is the same tile body as its own launch (one row block
+// per wave, one column or line block per tile), the workgroups take the
+// stage's tiles in turn, and a grid-wide barrier separates the stages, whose
+// release and acquire make each stage's outputs visible to the next.  A small
+// grid spends most of a launched step in launch and drain; here the fields
+// stay in the L2 and the MALL between stages.  Co-residency of the grid is
+// what the cooperative launch guarantees, so every barrier completes.
+// ---------------------------------------------------------------------------
+
+struct ResidentArgs {
+    OuterArgs outer[2];   // z then y (3-D), y (2-D)
+    long otiles[2];       // tiles of each outer stage
+    XArgs x;
+    long xtiles;          // tiles of the x stage
+    int nouter;
+    int nsteps;
+    double t0;
+};
+
+template <typename M, int NC, int MAXT>
+__global__ __launch_bounds__(MAXT) void resident_steps(ResidentArgs a) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    for (int s = 0; s < a.nsteps; ++s) {
+        for (int k = 0; k < a.nouter; ++k) {
+            OuterArgs o = a.outer[k];
+            group_time(o.rxn, a.t0, s);
+            for (long t = blockIdx.x; t < a.otiles[k]; t += gridDim.x) {
+                if (k == 0) outer_tile<M, NC, true, 1, 1>(o, t);
+                else outer_tile<M, NC, false, 1, 1>(o, t);
+                __syncthreads();   // the next tile restages the LDS
+            }
+            grid.sync();
+        }
+        XArgs x = a.x;
+        group_time(x.rxn, a.t0, s + 1);
+        for (long t = blockIdx.x; t < a.xtiles; t += gridDim.x) {
+            x_tile<M, NC, 1, 1>(x, t);
+            __syncthreads();
+        }
+        grid.sync();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // x stage of a two-component system whose joint tile exceeds the LDS: one
 // component at a time, in two kernels around W (written to memory), because
 // the reaction at W couples the components pointwise.

@@ -260,6 +260,42 @@ def test_tile_shapes_host_validation(etd):
         etd.etd_plan_destroy(plan)
 
 
+def test_schedule_host_validation(etd):
+    """The resident schedule (all steps in one cooperative launch) applies to
+    grids whose directions share one padded extent of at most 128; AUTO takes
+    it when no stage has more than 16 tiles of 16 columns or lines."""
+    cases = [((63, 63), "resident", True), ((64, 50), "resident", True), ((127, 120), "resident", True),
+             ((1, 1), "resident", True),
+             ((63, 63, 63), "stages", True), ((31, 20, 17), "stages", True),    # 256 and 64 tiles a stage
+             ((127, 127, 127), "stages", True),
+             ((63, 65), "stages", False), ((255, 255), "stages", False), ((63, 63, 80), "stages", False),
+             ((255, 255, 255), "stages", False)]
+    for n, auto, eligible in cases:
+        p = W.Problem(dim=len(n), n=n, kappa=(0.01,), tau=0.01, reaction="fisher")
+        plan = etd.etd_plan_create(p)
+        try:
+            assert etd.etd_plan_schedule(plan) == auto, n
+            etd.etd_plan_set_schedule(plan, "stages")
+            assert etd.etd_plan_schedule(plan) == "stages"
+            if eligible:
+                etd.etd_plan_set_schedule(plan, "resident")
+                assert etd.etd_plan_schedule(plan) == "resident"
+            else:
+                with pytest.raises(etd.EtdError) as ei:
+                    etd.etd_plan_set_schedule(plan, "resident")
+                assert ei.value.status == etd.ETD_EUNSUPPORTED
+                assert etd.etd_plan_schedule(plan) == "stages"      # unchanged
+            etd.etd_plan_set_schedule(plan, "auto")
+            assert etd.etd_plan_schedule(plan) == auto
+            for bad in (-1, 3, 7):
+                with pytest.raises(etd.EtdError) as ei:
+                    etd.etd_plan_set_schedule(plan, bad)
+                assert ei.value.status == etd.ETD_EINVAL
+            assert etd.etd_plan_schedule(plan) == auto
+        finally:
+            etd.etd_plan_destroy(plan)
+
+
 def test_bench_refuses_more_than_one_gpu():
     """The benchmark is a one-GPU measurement: --gpus above 1 exits with a
     message (before anything touches a device)."""

@@ -169,9 +169,11 @@ def roofline(wl, precision, ms, counts):
 
 
 def adjoint_leg(etd, torch, W, nsteps):
-    """Time one forward run and one adjoint (gradient w.r.t. u0, kappa, q)
-    over nsteps steps of the 3-D FitzHugh-Nagumo workload; the loss target is
-    u(T) of a run at 1.1 kappa_u."""
+    """Time one forward run and the adjoint (gradient w.r.t. u0, kappa, q) over
+    nsteps steps of the 3-D FitzHugh-Nagumo workload, with the shortest
+    checkpoint segment (ceil(sqrt(N)) steps: forward work about 2N steps) and
+    with one segment of N steps (every step's stage fields kept: one forward
+    pass); the loss target is u(T) of a run at 1.1 kappa_u."""
     wl = W.fhn3d(nsteps=nsteps)
     p = wl.problem
     st = etd.Stepper(p)
@@ -188,17 +190,28 @@ def adjoint_leg(etd, torch, W, nsteps):
     ubar = u - target
     st.adjoint(u0, ubar, 2)                            # warm the adjoint kernels
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, grad = st.adjoint(u0, ubar, nsteps)
-    torch.cuda.synchronize()
-    adj = time.perf_counter() - t0
+    out = {"workload": wl.name, "steps": nsteps, "precision": p.precision,
+           "forward_ms_per_step": 1e3 * fwd / nsteps}
+    grads = {}
+    for name, seg in (("sqrt_segments", math.ceil(math.sqrt(nsteps))), ("one_segment", nsteps)):
+        aws = st.adjoint_workspace(nsteps, seg)          # allocated outside the timed region
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, grad = st.adjoint(u0, ubar, nsteps, workspace=aws)
+        torch.cuda.synchronize()
+        adj = time.perf_counter() - t0
+        del aws
+        grads[name] = grad
+        out[name] = {"checkpoint_every": seg,
+                     "adjoint_workspace_gb": etd.etd_adjoint_workspace_bytes_segment(st.plan, nsteps, seg) / 1e9,
+                     "adjoint_ms_per_step": 1e3 * adj / nsteps, "adjoint_over_forward": adj / fwd,
+                     "adjoint_updates_per_s": p.npoints * nsteps / adj,
+                     "grad_kappa": grad[:p.ncomp], "grad_q": grad[p.ncomp]}
+        torch.cuda.empty_cache()
     st.close()
-    npts = p.npoints
-    return {"workload": wl.name, "steps": nsteps, "precision": p.precision,
-            "checkpoint_every": math.ceil(math.sqrt(nsteps)),
-            "forward_ms_per_step": 1e3 * fwd / nsteps, "adjoint_ms_per_step": 1e3 * adj / nsteps,
-            "adjoint_over_forward": adj / fwd, "adjoint_updates_per_s": npts * nsteps / adj,
-            "grad_kappa": grad[:p.ncomp], "grad_q": grad[p.ncomp]}
+    a, b = grads["sqrt_segments"], grads["one_segment"]
+    out["grad_rel_diff_between_segmentings"] = max(abs(x - y) / abs(y) for x, y in zip(a, b))
+    return out
 
 
 def batched_leg(etd, torch, W, nsteps):

@@ -173,16 +173,23 @@ etd_status etd_plan_table(const etd_plan* plan, int which, int d, int comp, doub
  * dL/dq.  Each stage's transpose is applied in reverse order (the step of
  * Sec. 3.1 with symmetric, commuting directional operators; the reaction
  * enters through its pointwise Jacobian); parameter derivatives use
- * dQ_l(tau lambda)/dlambda and dlambda/dkappa, dlambda/dq.  Forward states are
- * recomputed from ceil(sqrt(nsteps)) checkpoints held in the adjoint
- * workspace (etd_adjoint_workspace_bytes bytes, 256-byte aligned, caller-owned);
- * the plan's workspace is used as scratch.  Synchronises `stream`.  Gradients
+ * dQ_l(tau lambda)/dlambda and dlambda/dkappa, dlambda/dq.  Forward states
+ * come from checkpoints every K steps held in the adjoint workspace (256-byte
+ * aligned, caller-owned, adjoint_bytes long); each segment of K steps is
+ * replayed once, keeping every step's stage fields, so the forward work is
+ * (nsteps - K) + nsteps steps.  etd_adjoint takes the longest K whose layout
+ * fits adjoint_bytes: etd_adjoint_workspace_bytes is the smallest workspace
+ * (K = ceil(sqrt(nsteps))), etd_adjoint_workspace_bytes_segment the size for
+ * a given K between that and nsteps (ETD_EINVAL outside), and K = nsteps (one
+ * forward pass; about six fields per step in 3-D, four in 2-D) is the
+ * fastest.  The plan's workspace is used as scratch.  Synchronises `stream`.  Gradients
  * are summed in FP64 in a fixed order.  ETD_EUNSUPPORTED when the adjoint's
  * tiles exceed the on-chip limits: they hold four fields of one component,
  * so padded extents up to 288 with an FP64 state and 576 with an FP32 one
  * (and the forward x tile of all components must fit, as the replayed steps
  * keep W). */
 etd_status etd_adjoint_workspace_bytes(const etd_plan* plan, int nsteps, size_t* bytes);
+etd_status etd_adjoint_workspace_bytes_segment(const etd_plan* plan, int nsteps, int segment, size_t* bytes);
 etd_status etd_adjoint(const etd_plan* plan, const void* u0_dev, double t0, int nsteps, const void* ubar_final_dev,
                        void* ubar0_dev, double* grad, void* workspace_dev, void* adjoint_workspace_dev,
                        size_t adjoint_bytes, void* stream);

@@ -56,7 +56,7 @@ _lib = None
 EXPORTS = ("etd_plan_create", "etd_plan_workspace_bytes", "etd_plan_upload", "etd_advance", "etd_compare",
            "etd_compare_noalloc",
            "etd_plan_problem", "etd_plan_table", "etd_timing_enable", "etd_timing_read",
-           "etd_adjoint_workspace_bytes", "etd_adjoint",
+           "etd_adjoint_workspace_bytes", "etd_adjoint_workspace_bytes_segment", "etd_adjoint",
            "etd_plan_tiles", "etd_plan_set_tiles", "etd_plan_autotune",
            "etd_plan_set_schedule", "etd_plan_schedule",
            "etd_batch_create", "etd_batch_workspace_bytes", "etd_batch_upload", "etd_batch_advance",
@@ -87,6 +87,7 @@ def lib():
             "etd_timing_enable": [vp, ip],
             "etd_timing_read": [vp, dp, ctypes.POINTER(ctypes.c_longlong)],
             "etd_adjoint_workspace_bytes": [vp, ip, ctypes.POINTER(sz)],
+            "etd_adjoint_workspace_bytes_segment": [vp, ip, ip, ctypes.POINTER(sz)],
             "etd_adjoint": [vp, vp, d, ip, vp, vp, dp, vp, vp, sz, vp],
             "etd_plan_tiles": [vp, ipp],
             "etd_plan_set_tiles": [vp, ipp],
@@ -275,6 +276,13 @@ def etd_adjoint_workspace_bytes(plan, nsteps: int) -> int:
     return int(n.value)
 
 
+def etd_adjoint_workspace_bytes_segment(plan, nsteps: int, segment: int) -> int:
+    """Adjoint workspace for checkpoint segments of `segment` steps (segment = nsteps: one forward pass)."""
+    n = ctypes.c_size_t()
+    _check(lib().etd_adjoint_workspace_bytes_segment(plan, int(nsteps), int(segment), ctypes.byref(n)))
+    return int(n.value)
+
+
 def etd_adjoint(plan, u0, t0: float, nsteps: int, ubar_final, ubar0, workspace, adjoint_workspace, ncomp: int,
                 stream=None):
     """Returns [dL/dkappa_0, ..., dL/dkappa_{ncomp-1}, dL/dq]; writes dL/du0 into ubar0."""
@@ -441,13 +449,22 @@ class Stepper:
     def compare(self, a, b, allow_nonfinite=False):
         return etd_compare(self.plan, a, b, self.workspace, self.stream, allow_nonfinite)
 
-    def adjoint(self, u0, ubar_final, nsteps: int, t0: float = 0.0):
-        """(dL/du0, [dL/dkappa_c..., dL/dq]) for dL/dU_N = ubar_final."""
+    def adjoint_workspace(self, nsteps: int, segment: int = 0):
+        """A 256-byte-aligned device buffer for adjoint(..., segment=segment)."""
         import torch
-        nbytes = etd_adjoint_workspace_bytes(self.plan, nsteps)
+        nbytes = (etd_adjoint_workspace_bytes_segment(self.plan, nsteps, segment) if segment
+                  else etd_adjoint_workspace_bytes(self.plan, nsteps))
         raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-raw.data_ptr()) % 256
-        aws = raw[off:off + nbytes]
+        return raw[off:off + nbytes]
+
+    def adjoint(self, u0, ubar_final, nsteps: int, t0: float = 0.0, segment: int = 0, workspace=None):
+        """(dL/du0, [dL/dkappa_c..., dL/dq]) for dL/dU_N = ubar_final.  segment:
+        checkpoint segment length (0: the shortest, ceil(sqrt(nsteps)); nsteps:
+        every step's stage fields kept, one forward pass); the adjoint takes the
+        longest segment that fits `workspace` (allocated here when None)."""
+        import torch
+        aws = workspace if workspace is not None else self.adjoint_workspace(nsteps, segment)
         ubar0 = torch.empty(tuple(self.problem.shape), dtype=self.dtype, device=self.device)
         grad = etd_adjoint(self.plan, u0.contiguous(), t0, nsteps, ubar_final.contiguous(), ubar0, self.workspace,
                            aws, self.problem.ncomp, self.stream)

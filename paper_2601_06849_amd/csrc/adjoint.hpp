@@ -1,4 +1,4 @@
-// Host driver of the adjoint (sqrt(N) checkpointing).
+// Host driver of the adjoint (checkpointing in segments of sqrt(N) to N steps).
 //
 // Part of libetdds: included, in order, by library.hpp (each translation
 // unit that includes it holds its own copy); internal linkage throughout.
@@ -7,7 +7,7 @@
 namespace {
 
 // ---------------------------------------------------------------------------
-// Adjoint driver: sqrt(N) checkpointing
+// Adjoint driver: checkpoints every K steps, each segment replayed once
 // ---------------------------------------------------------------------------
 
 // gradient partial-sum arrays of the reverse sweep
@@ -34,9 +34,14 @@ size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr long kPointSlots = 2048;   // workgroups of the pointwise adjoint kernel
 
-AdjLayout adjoint_layout(const Plan& pl, int nsteps) {
+// Shortest checkpoint segment: ceil(sqrt(N)) steps.
+int min_segment(int nsteps) { return std::max(1, int(std::ceil(std::sqrt(double(std::max(nsteps, 1)))))); }
+
+// Layout for segments of K steps (0: the shortest).  The forward work is
+// N - K checkpointing steps plus N replayed ones, so K = N is one forward pass.
+AdjLayout adjoint_layout(const Plan& pl, int nsteps, int K = 0) {
     AdjLayout L;
-    L.K = std::max(1, int(std::ceil(std::sqrt(double(std::max(nsteps, 1))))));
+    L.K = K > 0 ? std::min(K, std::max(nsteps, 1)) : min_segment(nsteps);
     L.nck = (std::max(nsteps, 1) + L.K - 1) / L.K;
     L.field = pl.lay.field_bytes;
     const int ng = pl.nc + 1;
@@ -72,6 +77,19 @@ AdjLayout adjoint_layout(const Plan& pl, int nsteps) {
     off = a256(off + kAdjParts * size_t(ng) * 8);
     L.total = off;
     return L;
+}
+
+// The longest segment whose layout fits `bytes` (the layout grows with K from
+// the shortest segment on); the shortest if none does.
+int adjoint_segment_for(const Plan& pl, int nsteps, size_t bytes) {
+    int lo = min_segment(nsteps), hi = std::max(nsteps, 1);
+    if (adjoint_layout(pl, nsteps, lo).total > bytes) return lo;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (adjoint_layout(pl, nsteps, mid).total <= bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 // LDS of the adjoint tiles: the x kernels hold four and two fields of one

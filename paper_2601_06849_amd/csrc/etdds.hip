@@ -217,6 +217,17 @@ etd_status etd_adjoint_workspace_bytes(const etd_plan* plan, int nsteps, size_t*
     return ETD_OK;
 }
 
+etd_status etd_adjoint_workspace_bytes_segment(const etd_plan* plan, int nsteps, int segment, size_t* bytes) {
+    if (!plan || !bytes) return fail(ETD_EINVAL, "NULL argument");
+    if (nsteps < 1) return fail(ETD_EINVAL, "nsteps must be >= 1");
+    if (segment < min_segment(nsteps) || segment > nsteps)
+        return fail(ETD_EINVAL, "segment must lie between ceil(sqrt(nsteps)) and nsteps");
+    const etd_status st = adjoint_supported(plan->p);
+    if (st != ETD_OK) return st;
+    *bytes = adjoint_layout(plan->p, nsteps, segment).total;
+    return ETD_OK;
+}
+
 etd_status etd_adjoint(const etd_plan* plan, const void* u0, double t0, int nsteps, const void* ubar_final,
                        void* ubar0, double* grad, void* ws, void* adj_ws, size_t adj_bytes, void* stream) {
     if (!plan || !u0 || !ubar_final || !ubar0 || !grad) return fail(ETD_EINVAL, "NULL argument");
@@ -226,7 +237,8 @@ etd_status etd_adjoint(const etd_plan* plan, const void* u0, double t0, int nste
     if (st != ETD_OK) return st;
     st = adjoint_supported(plan->p);
     if (st != ETD_OK) return st;
-    const AdjLayout L = adjoint_layout(plan->p, nsteps);
+    const int segment = adjoint_segment_for(plan->p, nsteps, adj_bytes);
+    const AdjLayout L = adjoint_layout(plan->p, nsteps, segment);
     if (!adj_ws || reinterpret_cast<uintptr_t>(adj_ws) % 256 != 0)
         return fail(ETD_EWORKSPACE, "adjoint workspace must be non-NULL and 256-byte aligned");
     if (adj_bytes < L.total) return fail(ETD_EWORKSPACE, "adjoint workspace smaller than etd_adjoint_workspace_bytes()");
@@ -234,7 +246,8 @@ etd_status etd_adjoint(const etd_plan* plan, const void* u0, double t0, int nste
     char* w = static_cast<char*>(ws);
     char* a = static_cast<char*>(adj_ws);
     const Plan& pl = plan->p;
-    return ops_for(pl.prob.precision).adjoint(pl, plan->timer, u0, t0, nsteps, ubar_final, ubar0, grad, w, a, s);
+    return ops_for(pl.prob.precision).adjoint(pl, plan->timer, u0, t0, nsteps, segment, ubar_final, ubar0, grad, w, a,
+                                              s);
 }
 
 etd_status etd_plan_autotune(etd_plan* plan, void* ws, void* stream) {

@@ -13,9 +13,9 @@ etd_status op_advance(const Plan& pl, StageTimer& tm, void* u, double t0, int ns
 }
 
 template <typename M>
-etd_status op_adjoint(const Plan& pl, StageTimer& tm, const void* u0, double t0, int nsteps, const void* ubarN,
-                      void* ubar0, double* grad, char* ws, char* aws, hipStream_t s) {
-    const AdjLayout L = adjoint_layout(pl, nsteps);
+etd_status op_adjoint(const Plan& pl, StageTimer& tm, const void* u0, double t0, int nsteps, int segment,
+                      const void* ubarN, void* ubar0, double* grad, char* ws, char* aws, hipStream_t s) {
+    const AdjLayout L = adjoint_layout(pl, nsteps, segment);
     return pl.nc == 1 ? adjoint_t<M, 1>(pl, tm, u0, t0, nsteps, ubarN, ubar0, grad, ws, aws, L, s)
                       : adjoint_t<M, 2>(pl, tm, u0, t0, nsteps, ubarN, ubar0, grad, ws, aws, L, s);
 }

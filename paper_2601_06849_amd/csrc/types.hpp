@@ -70,8 +70,8 @@ struct Batch {
 struct PrecisionOps {
     // etd_advance: pack, nsteps steps, unpack (ws: the uploaded workspace)
     etd_status (*advance)(const Plan& pl, StageTimer& tm, void* u, double t0, int nsteps, char* ws, hipStream_t s);
-    // etd_adjoint (aws: the adjoint workspace of adjoint_layout(pl, nsteps))
-    etd_status (*adjoint)(const Plan& pl, StageTimer& tm, const void* u0, double t0, int nsteps,
+    // etd_adjoint (aws: the adjoint workspace of adjoint_layout(pl, nsteps, segment))
+    etd_status (*adjoint)(const Plan& pl, StageTimer& tm, const void* u0, double t0, int nsteps, int segment,
                           const void* ubar_final, void* ubar0, double* grad, char* ws, char* aws, hipStream_t s);
     etd_status (*autotune)(Plan& pl, char* ws, hipStream_t s);
     // validate a tile request for direction d ((0, 0): the default shape)

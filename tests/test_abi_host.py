@@ -204,6 +204,16 @@ def test_adjoint_workspace_query(etd):
         with pytest.raises(etd.EtdError) as ei:
             etd.etd_adjoint_workspace_bytes(plan, 0)
         assert ei.value.status == etd.ETD_EINVAL
+        # checkpoint segments of 20 (the shortest) to 400 steps (one forward
+        # pass keeping five stage fields and the state of every step)
+        assert etd.etd_adjoint_workspace_bytes_segment(plan, 400, 20) == n1
+        full = etd.etd_adjoint_workspace_bytes_segment(plan, 400, 400)
+        field = 2 * 128 ** 3 * 4
+        assert 6 * 400 * field < full < 6 * 400 * field + 16 * field
+        for bad in (19, 401, -1):
+            with pytest.raises(etd.EtdError) as ei:
+                etd.etd_adjoint_workspace_bytes_segment(plan, 400, bad)
+            assert ei.value.status == etd.ETD_EINVAL
     finally:
         etd.etd_plan_destroy(plan)
     for prec, n_ok, n_big in (("fp64", (255, 40, 288), (300, 40, 40)), ("fp64_fp32", (288, 255, 30), (30, 320, 30)),

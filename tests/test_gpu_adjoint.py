@@ -290,3 +290,34 @@ def test_autograd_fp32_problem_with_float64_u0(etd):
     st.close()
     assert torch.equal(u0.grad, ubar0.double())
     assert kappa.grad.tolist() == grad[:2] and float(q.grad) == grad[2]
+
+
+@pytest.mark.parametrize("dim,precision", [(3, "fp64"), (2, "fp32"), (3, "fp64_bf16x6")])
+def test_adjoint_segment_lengths_agree(etd, dim, precision):
+    """Checkpoint segments of ceil(sqrt(N)), an intermediate length and N steps
+    (one forward pass that keeps every step's stage fields) replay the same
+    states with the same kernels, so the gradients agree bit for bit; a
+    workspace between two layouts' sizes takes the longer segment that fits."""
+    import torch
+    if dim == 3:
+        p = W.fhn3d(n=31, nsteps=20, precision=precision).problem
+    else:
+        p = W.Problem(dim=2, n=(60, 45), kappa=(0.01, 0.002), q=0.1, tau=0.05, reaction="fhn_cubic",
+                      precision=precision)
+    N = 20
+    st = etd.Stepper(p)
+    u0 = st.field(W.u0_fhn_patch(p, 5, patch=0.4))
+    ub = st.advance(u0.clone(), N) - 0.5
+    sizes = [etd.etd_adjoint_workspace_bytes_segment(st.plan, N, k) for k in (5, 6, 7, 11, 20)]
+    assert sizes[0] == etd.etd_adjoint_workspace_bytes(st.plan, N)
+    assert sizes == sorted(sizes) and sizes[0] < sizes[-1]
+    for bad in (4, 21, 0):
+        with pytest.raises(etd.EtdError) as ei:
+            etd.etd_adjoint_workspace_bytes_segment(st.plan, N, bad)
+        assert ei.value.status == etd.ETD_EINVAL
+    ref0, ref = st.adjoint(u0, ub, N)
+    for seg in (7, 11, 20):
+        b0, g = st.adjoint(u0, ub, N, segment=seg)
+        assert torch.equal(b0, ref0), seg
+        assert g == ref, seg
+    st.close()

@@ -109,16 +109,33 @@ etd_status adjoint_supported(const Plan& pl) {
     return ETD_OK;
 }
 
-template <typename M, int NC, int RB, int MAXT, bool SECOND>
-etd_status launch_xadj_k(const XAdjArgs& a, long nlines, hipStream_t s) {
+// Two line or column blocks per adjoint tile where its four fields fit
+// (each P fragment then feeds twice the MFMAs): up to NP = 128 in FP32 and
+// FP64 states.
+int adjoint_cb(int NP, size_t elem) {
+    return NP <= 128 && x_lds_bytes(NP, 4, 2, elem) + kStaticLds <= kMaxLds ? 2 : 1;
+}
+
+template <typename M, int NC, int RB, int CB, int MAXT, bool SECOND>
+etd_status launch_xadj_cb(const XAdjArgs& a, long nlines, hipStream_t s) {
     typedef typename M::elem T;
-    const size_t lds = x_adjoint_lds(a.NP, sizeof(T), SECOND);
-    auto k = SECOND ? x_adjoint_w<M, NC, RB, MAXT> : x_adjoint_g<M, NC, RB, MAXT>;
+    const size_t lds = x_lds_bytes(a.NP, SECOND ? 2 : 4, CB, sizeof(T));
+    auto k = SECOND ? x_adjoint_w<M, NC, RB, CB, MAXT> : x_adjoint_g<M, NC, RB, CB, MAXT>;
     static size_t done = 0;
     HIP_TRY(set_lds(k, lds, done), "adjoint x LDS attribute");
-    hipLaunchKernelGGL(k, dim3(unsigned(nlines / 16), unsigned(NC)), dim3(shape_threads(a.NP, RB)), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(unsigned(nlines / (16 * CB)), unsigned(NC)), dim3(shape_threads(a.NP, RB)), lds, s,
+                       a);
     HIP_TRY(hipGetLastError(), "adjoint x launch");
     return ETD_OK;
+}
+
+template <typename M, int NC, int RB, int MAXT, bool SECOND>
+etd_status launch_xadj_k(const XAdjArgs& a, long nlines, hipStream_t s) {
+    if constexpr (RB == 1 && MAXT <= 512) {   // the shape of NP <= 128
+        if (adjoint_cb(a.NP, sizeof(typename M::elem)) == 2 && nlines % 32 == 0)
+            return launch_xadj_cb<M, NC, RB, 2, MAXT, SECOND>(a, nlines, s);
+    }
+    return launch_xadj_cb<M, NC, RB, 1, MAXT, SECOND>(a, nlines, s);
 }
 #define XADJ_K(RB, MAXT, M, NC, SECOND, a, nl, s) launch_xadj_k<M, NC, RB, MAXT, SECOND>(a, nl, s)
 
@@ -128,16 +145,26 @@ etd_status launch_xadj_k(const XAdjArgs& a, long nlines, hipStream_t s) {
 // earlier joint tiles).
 #define ADJ_SHAPE(NP, KERNEL, ...) ((NP) <= 128 ? KERNEL(1, 512, __VA_ARGS__) : DISPATCH_SHAPE(NP, KERNEL, __VA_ARGS__))
 
-template <typename M, int NC, bool FIRST, int RB, int MAXT>
-etd_status launch_oadj_k(const OuterAdjArgs& a, long nblocks, hipStream_t s) {
+template <typename M, int NC, bool FIRST, int RB, int CB, int MAXT>
+etd_status launch_oadj_cb(OuterAdjArgs a, long nblocks, hipStream_t s) {
     typedef typename M::elem T;
-    const size_t lds = outer_adjoint_lds(a.NP, sizeof(T));
-    auto k = outer_adjoint<M, NC, FIRST, RB, MAXT>;
+    const size_t lds = outer_lds_bytes(a.NP, 4, CB, sizeof(T));
+    auto k = outer_adjoint<M, NC, FIRST, RB, CB, MAXT>;
     static size_t done = 0;
     HIP_TRY(set_lds(k, lds, done), "adjoint outer LDS attribute");
-    hipLaunchKernelGGL(k, dim3(unsigned(nblocks), unsigned(NC)), dim3(shape_threads(a.NP, RB)), lds, s, a);
+    a.ncb /= CB;
+    hipLaunchKernelGGL(k, dim3(unsigned(nblocks / CB), unsigned(NC)), dim3(shape_threads(a.NP, RB)), lds, s, a);
     HIP_TRY(hipGetLastError(), "adjoint outer launch");
     return ETD_OK;
+}
+
+template <typename M, int NC, bool FIRST, int RB, int MAXT>
+etd_status launch_oadj_k(const OuterAdjArgs& a, long nblocks, hipStream_t s) {
+    if constexpr (RB == 1 && MAXT <= 512) {
+        if (adjoint_cb(a.NP, sizeof(typename M::elem)) == 2 && a.ncb % 2 == 0)
+            return launch_oadj_cb<M, NC, FIRST, RB, 2, MAXT>(a, nblocks, s);
+    }
+    return launch_oadj_cb<M, NC, FIRST, RB, 1, MAXT>(a, nblocks, s);
 }
 #define OADJ_K(RB, MAXT, M, NC, FIRST, a, nb, s) launch_oadj_k<M, NC, FIRST, RB, MAXT>(a, nb, s)
 

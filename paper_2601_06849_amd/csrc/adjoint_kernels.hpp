@@ -77,12 +77,13 @@ struct XAdjArgs {
     GradArgs grad;
 };
 
-// x-direction adjoint, part (a), component blockIdx.y over 16 lines.  LDS: 4
-// fields [16 lines][NP + pad]: U+bar, w, v and d = f(W) - v (formed while
+// x-direction adjoint, part (a), component blockIdx.y over 16*CB lines.  LDS:
+// 4 fields [16*CB lines][NP + pad]: U+bar, w, v and d = f(W) - v (formed while
 // staging), then (q3 - 1/2) P U+bar.  Writes g and the weights
 // h = (P w) rho1 + (P v) rho2 that part (b) pairs with P Wbar, and adds the
-// <U+bar, dQ3x d> gradient terms.
-template <typename M, int NC, int RB, int MAXT>
+// <U+bar, dQ3x d> gradient terms.  B fragment qq of a product is field qq / CB,
+// line block qq % CB, so each P fragment feeds CB times as many MFMAs.
+template <typename M, int NC, int RB, int CB, int MAXT>
 __global__ __launch_bounds__(MAXT) void x_adjoint_g(XAdjArgs a) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
@@ -90,17 +91,18 @@ __global__ __launch_bounds__(MAXT) void x_adjoint_g(XAdjArgs a) {
     typedef typename Vec4<AT>::type A4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
+    constexpr int NL = 16 * CB;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* R = reinterpret_cast<T*>(smem_raw);
     const int NP = a.NP;
     const int RS = NP + 16 / int(sizeof(T));
-    const int AST = 16 * RS;
+    const int AST = NL * RS;
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
     const int c = blockIdx.y;
-    const long line0 = long(blockIdx.x) * 16;
+    const long line0 = long(blockIdx.x) * NL;
     const long cs = c * a.sc;
     const void* __restrict__ P = a.P;
     const T tau = T(a.tau);
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(MAXT) void x_adjoint_g(XAdjArgs a) {
     const T* wf = static_cast<const T*>(a.w);
     const T* vf = static_cast<const T*>(a.v);
 #pragma unroll 2
-    for (int v = tid; v < 16 * vpl; v += blockDim.x) {
+    for (int v = tid; v < NL * vpl; v += blockDim.x) {
         const int j = v / vpl, x = (v - j * vpl) * VN;
         const long gi = line0 * NP + long(v) * VN;
         const long line = line0 + j;
@@ -137,70 +139,83 @@ __global__ __launch_bounds__(MAXT) void x_adjoint_g(XAdjArgs a) {
     }
     __syncthreads();
     const int rb0 = RB * w;
-    auto bfrag = [&](int q, int k0) { return lds_vec<T, M::KL>(R + q * AST + li * RS + k0); };
-    auto at = [&](int q, int r, int e) -> T& { return R[q * AST + li * RS + 16 * (rb0 + r) + M::row(lg, e)]; };
+    auto bfrag = [&](int qq, int k0) {
+        return lds_vec<T, M::KL>(R + (qq / CB) * AST + ((qq % CB) * 16 + li) * RS + k0);
+    };
+    auto at = [&](int qq, int r, int e) -> T& {
+        return R[(qq / CB) * AST + ((qq % CB) * 16 + li) * RS + 16 * (rb0 + r) + M::row(lg, e)];
+    };
     const T* __restrict__ d3 = static_cast<const T*>(a.diag) + c * a.diag_cstride + 2 * a.diag_sstride;
     const double* wt = a.grad.table + c * (3L * kGradSlots * kMaxPadded) + (long(a.grad.dir) * kGradSlots) * kMaxPadded;
-    const long line = line0 + li;
     double gacc[NC + 1];
 #pragma unroll
     for (int k = 0; k <= NC; ++k) gacc[k] = 0.0;
 
     // ---- S1 = P U+bar, Sw = P w, Sv = P v, Sd = P d ----
-    T4 ub[RB];
+    T4 ub[RB][CB];
     {
-        A4 acc[RB][4];
-        zero<AT, RB, 4>(acc);
-        gemm<M, RB, 4>(P, NP, rb0, li, lg, acc, bfrag);
-        T* __restrict__ ho = static_cast<T*>(a.h) + cs + line * NP + 16 * rb0;
+        A4 acc[RB][4 * CB];
+        zero<AT, RB, 4 * CB>(acc);
+        gemm<M, RB, 4 * CB>(P, NP, rb0, li, lg, acc, bfrag);
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
+        for (int b = 0; b < CB; ++b) {
+            T* __restrict__ ho = static_cast<T*>(a.h) + cs + (line0 + 16 * b + li) * NP + 16 * rb0;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = 16 * (rb0 + r) + M::row(lg, e);
-                ub[r][e] = at(0, r, e);
-                const double t3 = double(acc[r][0][e]) * double(acc[r][3][e]) * wt[kGradRho3 * kMaxPadded + k];
-                gacc[c] += t3 * wt[kGradMu * kMaxPadded + k];
-                gacc[NC] += t3 * a.grad.inv_dim;
-                ho[16 * r + M::row(lg, e)] = T(double(acc[r][1][e]) * wt[kGradRho1 * kMaxPadded + k] +
-                                               double(acc[r][2][e]) * wt[kGradRho2 * kMaxPadded + k]);
-            }
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = 16 * (rb0 + r) + M::row(lg, e);
+                    ub[r][b][e] = at(b, r, e);
+                    const double t3 = double(acc[r][b][e]) * double(acc[r][3 * CB + b][e]) *
+                                      wt[kGradRho3 * kMaxPadded + k];
+                    gacc[c] += t3 * wt[kGradMu * kMaxPadded + k];
+                    gacc[NC] += t3 * a.grad.inv_dim;
+                    ho[16 * r + M::row(lg, e)] = T(double(acc[r][CB + b][e]) * wt[kGradRho1 * kMaxPadded + k] +
+                                                   double(acc[r][2 * CB + b][e]) * wt[kGradRho2 * kMaxPadded + k]);
+                }
+        }
         __syncthreads();
         // (q3 - 1/2) S1 over U+bar
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
+        for (int b = 0; b < CB; ++b)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) at(0, r, e) = d3[16 * (rb0 + r) + M::row(lg, e)] * acc[r][0][e];
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) at(b, r, e) = d3[16 * (rb0 + r) + M::row(lg, e)] * acc[r][b][e];
     }
     __syncthreads();
 
     // ---- g = tau (U+bar / 2 + P ((q3 - 1/2) S1)) ----
-    A4 acc[RB][1];
-    zero<AT, RB, 1>(acc);
-    gemm<M, RB, 1>(P, NP, rb0, li, lg, acc, bfrag);
-    T* __restrict__ go = static_cast<T*>(a.g) + cs + line * NP + 16 * rb0;
-    const int y = int(line % a.npy), z = int(line / a.npy);
+    A4 acc[RB][CB];
+    zero<AT, RB, CB>(acc);
+    gemm<M, RB, CB>(P, NP, rb0, li, lg, acc, bfrag);
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+    for (int b = 0; b < CB; ++b) {
+        const long line = line0 + 16 * b + li;
+        T* __restrict__ go = static_cast<T*>(a.g) + cs + line * NP + 16 * rb0;
+        const int y = int(line % a.npy), z = int(line / a.npy);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const T gg = tau * (T(0.5) * ub[r][e] + acc[r][0][e]);
-            go[16 * r + M::row(lg, e)] = gg;
-            if (a.rxn.kind == ETD_RXN_AC_MMS) {   // psi(t_{n+1}) depends on kappa and q
-                const double ue = ac_ue(a.rxn, 16 * (rb0 + r) + M::row(lg, e), y, z) * double(gg);
-                gacc[0] += a.rxn.ac_mu * ue;
-                gacc[NC] += ue;
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const T gg = tau * (T(0.5) * ub[r][b][e] + acc[r][b][e]);
+                go[16 * r + M::row(lg, e)] = gg;
+                if (a.rxn.kind == ETD_RXN_AC_MMS) {   // psi(t_{n+1}) depends on kappa and q
+                    const double ue = ac_ue(a.rxn, 16 * (rb0 + r) + M::row(lg, e), y, z) * double(gg);
+                    gacc[0] += a.rxn.ac_mu * ue;
+                    gacc[NC] += ue;
+                }
             }
-        }
+    }
     add_partials<NC + 1>(gacc, a.grad.partial, grid_slot());
 }
 
-// x-direction adjoint, part (b), component blockIdx.y over 16 lines.  LDS: 2
-// fields: Wbar = U+bar + J(W)^T g (formed while staging), then the scaled
+// x-direction adjoint, part (b), component blockIdx.y over 16*CB lines.  LDS:
+// 2 fields: Wbar = U+bar + J(W)^T g (formed while staging), then the scaled
 // coefficients (q1 - 1) P Wbar and tau (q2 - 1) P Wbar.  Adds the
 // <Wbar, dQ1x w> + tau <Wbar, dQ2x v> gradient terms and writes
 // wbar = Q1x Wbar and vbar = tau Q2x Wbar - g.
-template <typename M, int NC, int RB, int MAXT>
+template <typename M, int NC, int RB, int CB, int MAXT>
 __global__ __launch_bounds__(MAXT) void x_adjoint_w(XAdjArgs a) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
@@ -208,17 +223,18 @@ __global__ __launch_bounds__(MAXT) void x_adjoint_w(XAdjArgs a) {
     typedef typename Vec4<AT>::type A4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
+    constexpr int NL = 16 * CB;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* R = reinterpret_cast<T*>(smem_raw);
     const int NP = a.NP;
     const int RS = NP + 16 / int(sizeof(T));
-    const int AST = 16 * RS;
+    const int AST = NL * RS;
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
     const int c = blockIdx.y;
-    const long line0 = long(blockIdx.x) * 16;
+    const long line0 = long(blockIdx.x) * NL;
     const long cs = c * a.sc;
     const void* __restrict__ P = a.P;
     const T tau = T(a.tau);
@@ -227,7 +243,7 @@ __global__ __launch_bounds__(MAXT) void x_adjoint_w(XAdjArgs a) {
     const T* Wf = static_cast<const T*>(a.W);
     const T* gf = static_cast<const T*>(a.g);
 #pragma unroll 2
-    for (int v = tid; v < 16 * vpl; v += blockDim.x) {
+    for (int v = tid; v < NL * vpl; v += blockDim.x) {
         const int j = v / vpl, x = (v - j * vpl) * VN;
         const long gi = line0 * NP + long(v) * VN;
         const TV ub = *reinterpret_cast<const TV*>(ubar + cs + gi);
@@ -253,61 +269,72 @@ __global__ __launch_bounds__(MAXT) void x_adjoint_w(XAdjArgs a) {
     }
     __syncthreads();
     const int rb0 = RB * w;
-    auto bfrag = [&](int q, int k0) { return lds_vec<T, M::KL>(R + q * AST + li * RS + k0); };
-    auto at = [&](int q, int r, int e) -> T& { return R[q * AST + li * RS + 16 * (rb0 + r) + M::row(lg, e)]; };
+    auto bfrag = [&](int qq, int k0) {
+        return lds_vec<T, M::KL>(R + (qq / CB) * AST + ((qq % CB) * 16 + li) * RS + k0);
+    };
+    auto at = [&](int qq, int r, int e) -> T& {
+        return R[(qq / CB) * AST + ((qq % CB) * 16 + li) * RS + 16 * (rb0 + r) + M::row(lg, e)];
+    };
     const T* __restrict__ d1 = static_cast<const T*>(a.diag) + c * a.diag_cstride;
     const T* __restrict__ d2 = d1 + a.diag_sstride;
     const double* wt = a.grad.table + c * (3L * kGradSlots * kMaxPadded) + (long(a.grad.dir) * kGradSlots) * kMaxPadded;
-    const long line = line0 + li;
-    const long o = cs + line * NP + 16 * rb0;
     double gacc[NC + 1];
 #pragma unroll
     for (int k = 0; k <= NC; ++k) gacc[k] = 0.0;
 
     // ---- S2 = P Wbar; gradient terms against h; scaled coefficients ----
-    T4 wb[RB];
+    T4 wb[RB][CB];
     {
-        A4 acc[RB][1];
-        zero<AT, RB, 1>(acc);
-        gemm<M, RB, 1>(P, NP, rb0, li, lg, acc, bfrag);
-        const T* __restrict__ hi = static_cast<const T*>(a.h) + o;
+        A4 acc[RB][CB];
+        zero<AT, RB, CB>(acc);
+        gemm<M, RB, CB>(P, NP, rb0, li, lg, acc, bfrag);
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
+        for (int b = 0; b < CB; ++b) {
+            const T* __restrict__ hi = static_cast<const T*>(a.h) + cs + (line0 + 16 * b + li) * NP + 16 * rb0;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = 16 * (rb0 + r) + M::row(lg, e);
-                wb[r][e] = at(0, r, e);
-                const double t = double(acc[r][0][e]) * double(hi[16 * r + M::row(lg, e)]);
-                gacc[c] += t * wt[kGradMu * kMaxPadded + k];
-                gacc[NC] += t * a.grad.inv_dim;
-            }
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = 16 * (rb0 + r) + M::row(lg, e);
+                    wb[r][b][e] = at(b, r, e);
+                    const double t = double(acc[r][b][e]) * double(hi[16 * r + M::row(lg, e)]);
+                    gacc[c] += t * wt[kGradMu * kMaxPadded + k];
+                    gacc[NC] += t * a.grad.inv_dim;
+                }
+        }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
+        for (int b = 0; b < CB; ++b)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = 16 * (rb0 + r) + M::row(lg, e);
-                at(0, r, e) = d1[k] * acc[r][0][e];   // (q1 - 1) S2
-                at(1, r, e) = d2[k] * acc[r][0][e];   // tau (q2 - 1) S2
-            }
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = 16 * (rb0 + r) + M::row(lg, e);
+                    at(b, r, e) = d1[k] * acc[r][b][e];        // (q1 - 1) S2
+                    at(CB + b, r, e) = d2[k] * acc[r][b][e];   // tau (q2 - 1) S2
+                }
     }
     __syncthreads();
 
     // ---- wbar = Wbar + P ((q1 - 1) S2); vbar = -g + tau Wbar + P (tau (q2 - 1) S2) ----
-    A4 acc[RB][2];
-    zero<AT, RB, 2>(acc);
-    gemm<M, RB, 2>(P, NP, rb0, li, lg, acc, bfrag);
-    T* __restrict__ ow = static_cast<T*>(a.wbar) + o;
-    T* __restrict__ ov = static_cast<T*>(a.vbar) + o;
-    const T* __restrict__ gi = gf + o;
+    A4 acc[RB][2 * CB];
+    zero<AT, RB, 2 * CB>(acc);
+    gemm<M, RB, 2 * CB>(P, NP, rb0, li, lg, acc, bfrag);
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+    for (int b = 0; b < CB; ++b) {
+        const long o = cs + (line0 + 16 * b + li) * NP + 16 * rb0;
+        T* __restrict__ ow = static_cast<T*>(a.wbar) + o;
+        T* __restrict__ ov = static_cast<T*>(a.vbar) + o;
+        const T* __restrict__ gi = gf + o;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int x = 16 * r + M::row(lg, e);
-            ow[x] = wb[r][e] + acc[r][0][e];
-            ov[x] = -gi[x] + tau * wb[r][e] + acc[r][1][e];
-        }
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = 16 * r + M::row(lg, e);
+                ow[x] = wb[r][b][e] + acc[r][b][e];
+                ov[x] = -gi[x] + tau * wb[r][b][e] + acc[r][CB + b][e];
+            }
+    }
     add_partials<NC + 1>(gacc, a.grad.partial, grid_slot());
 }
 
@@ -330,9 +357,10 @@ struct OuterAdjArgs {
 
 // Adjoint of an outer stage (z or y) for component blockIdx.y: the forward
 // stage applied to the two adjoint fields, plus the gradient terms
-// <a, dQ1 f> against the forward partners.  LDS: 4 fields [16 columns][NP +
-// pad]: a0, a1, f0, f1.
-template <typename M, int NC, bool FIRST, int RB, int MAXT>
+// <a, dQ1 f> against the forward partners.  LDS: 4 fields [16*CB columns][NP +
+// pad]: a0, a1, f0, f1; B fragment qq is field qq / CB, column block qq % CB.
+// a.ncb counts tiles of 16*CB columns per batch.
+template <typename M, int NC, bool FIRST, int RB, int CB, int MAXT>
 __global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
     typedef typename M::elem T;
     typedef typename Vec4<T>::type T4;
@@ -340,12 +368,13 @@ __global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
     typedef typename Vec4<AT>::type A4;
     typedef typename Vec16<T>::type TV;
     constexpr int VN = Vec16<T>::n;
-    constexpr int VPR = 16 / VN;
+    constexpr int NCOL = 16 * CB;
+    constexpr int VPR = NCOL / VN;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* X = reinterpret_cast<T*>(smem_raw);
     const int NP = a.NP;
     const int RS = NP + 16 / int(sizeof(T));
-    const int AST = 16 * RS;
+    const int AST = NCOL * RS;
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
@@ -354,7 +383,7 @@ __global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
     const long cs = c * a.sc;
     const int cb = blockIdx.x % a.ncb;
     const long bt = blockIdx.x / a.ncb;
-    const long gbase = bt * a.sb + long(cb) * 16;
+    const long gbase = bt * a.sb + long(cb) * NCOL;
     const void* __restrict__ P = a.P;
     const T* a0 = static_cast<const T*>(a.a0);
     const T* a1 = static_cast<const T*>(a.a1);
@@ -374,7 +403,7 @@ __global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
             fa = uk[c];
 #pragma unroll
             for (int t = 0; t < VN; ++t) {
-                const int col = cb * 16 + j0 + t;
+                const int col = cb * NCOL + j0 + t;
                 int x, y, z;
                 if (a.dim == 3) {
                     z = k;
@@ -405,54 +434,66 @@ __global__ __launch_bounds__(MAXT) void outer_adjoint(OuterAdjArgs a) {
     }
     __syncthreads();
     const int rb0 = RB * w;
-    auto bfrag = [&](int q, int k0) { return lds_vec<T, M::KL>(X + q * AST + li * RS + k0); };
-    auto at = [&](int q, int r, int e) -> T& { return X[q * AST + li * RS + 16 * (rb0 + r) + M::row(lg, e)]; };
+    auto bfrag = [&](int qq, int k0) {
+        return lds_vec<T, M::KL>(X + (qq / CB) * AST + ((qq % CB) * 16 + li) * RS + k0);
+    };
+    auto at = [&](int qq, int r, int e) -> T& {
+        return X[(qq / CB) * AST + ((qq % CB) * 16 + li) * RS + 16 * (rb0 + r) + M::row(lg, e)];
+    };
     const T* __restrict__ dc = static_cast<const T*>(a.diag) + c * a.diag_cstride;
     const double* wt = a.grad.table + c * (3L * kGradSlots * kMaxPadded) + (long(a.grad.dir) * kGradSlots) * kMaxPadded;
     double gacc[NC + 1];
 #pragma unroll
     for (int k = 0; k <= NC; ++k) gacc[k] = 0.0;
-    T4 res[RB][2];
+    T4 res[RB][2 * CB];
     {
-        A4 acc[RB][4];
-        zero<AT, RB, 4>(acc);
-        gemm<M, RB, 4>(P, NP, rb0, li, lg, acc, bfrag);
+        A4 acc[RB][4 * CB];
+        zero<AT, RB, 4 * CB>(acc);
+        gemm<M, RB, 4 * CB>(P, NP, rb0, li, lg, acc, bfrag);
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
+        for (int b = 0; b < CB; ++b)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = 16 * (rb0 + r) + M::row(lg, e);
-                const double t = (double(acc[r][0][e]) * acc[r][2][e] + double(acc[r][1][e]) * acc[r][3][e]) *
-                                 wt[kGradRho1 * kMaxPadded + k];
-                gacc[c] += t * wt[kGradMu * kMaxPadded + k];
-                gacc[NC] += t * a.grad.inv_dim;
-                res[r][0][e] = at(0, r, e);
-                res[r][1][e] = at(1, r, e);
-            }
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = 16 * (rb0 + r) + M::row(lg, e);
+                    const double t = (double(acc[r][b][e]) * acc[r][2 * CB + b][e] +
+                                      double(acc[r][CB + b][e]) * acc[r][3 * CB + b][e]) *
+                                     wt[kGradRho1 * kMaxPadded + k];
+                    gacc[c] += t * wt[kGradMu * kMaxPadded + k];
+                    gacc[NC] += t * a.grad.inv_dim;
+                    res[r][b][e] = at(b, r, e);
+                    res[r][CB + b][e] = at(CB + b, r, e);
+                }
         __syncthreads();
 #pragma unroll
+        for (int b = 0; b < CB; ++b)
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const T d = dc[16 * (rb0 + r) + M::row(lg, e)];
+                    at(b, r, e) = acc[r][b][e] * d;
+                    at(CB + b, r, e) = acc[r][CB + b][e] * d;
+                }
+    }
+    __syncthreads();
+    A4 acc[RB][2 * CB];
+    zero<AT, RB, 2 * CB>(acc);
+    gemm<M, RB, 2 * CB>(P, NP, rb0, li, lg, acc, bfrag);
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+        T* __restrict__ o0 = static_cast<T*>(a.out0) + cs + gbase + 16 * b + li;
+        T* __restrict__ o1 = static_cast<T*>(a.out1) + cs + gbase + 16 * b + li;
+#pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const T d = dc[16 * (rb0 + r) + M::row(lg, e)];
-                at(0, r, e) = acc[r][0][e] * d;
-                at(1, r, e) = acc[r][1][e] * d;
+                const long row = long(16 * (rb0 + r) + M::row(lg, e)) * a.sk;
+                o0[row] = res[r][b][e] + acc[r][b][e];
+                o1[row] = res[r][CB + b][e] + acc[r][CB + b][e];
             }
     }
-    __syncthreads();
-    A4 acc[RB][2];
-    zero<AT, RB, 2>(acc);
-    gemm<M, RB, 2>(P, NP, rb0, li, lg, acc, bfrag);
-    T* __restrict__ o0 = static_cast<T*>(a.out0) + cs + gbase + li;
-    T* __restrict__ o1 = static_cast<T*>(a.out1) + cs + gbase + li;
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const long row = long(16 * (rb0 + r) + M::row(lg, e)) * a.sk;
-            o0[row] = res[r][0][e] + acc[r][0][e];
-            o1[row] = res[r][1][e] + acc[r][1][e];
-        }
     add_partials<NC + 1>(gacc, a.grad.partial, grid_slot());
 }
 

@@ -631,14 +631,19 @@ etd_status run_steps_split2d(const Plan& pl, StageTimer& tm, char* ws, double t0
 // Resident schedule: every step of a run in one cooperative launch, for grids
 // whose directions share one padded extent of at most kResidentMaxNP points
 // (fused tiles of one row block per wave and one column or line block: NP/16
-// waves).  AUTO takes it when no stage has more than kResidentAutoTiles tiles,
-// outside graph capture and stage timing.  Measured per step (FP64 Fisher-KPP,
+// waves).  AUTO takes it when no stage has more than kResidentAutoTiles tiles
+// and a call has at least kResidentAutoSteps steps, outside graph capture and
+// stage timing.  Measured per step (FP64 Fisher-KPP,
 // whole-run calls): 31^2 13.5 -> 10.7 us, 63^2 21.3 -> 15.1 us, 127^2 48.5 ->
 // 34.9 us; but 31^3 (64 tiles) 21.1 -> 35.6 us and 63^3 (256 tiles) 33.7 ->
 // 108 us, since the grid-wide barrier's cost grows with the workgroup count.
 constexpr int kResidentMaxNP = 128;
 constexpr int kResidentThreads = 512;
 constexpr long kResidentAutoTiles = 16;
+// ... and only for calls of at least this many steps: a cooperative launch
+// costs 40-180 us of host time, against 15 us per resident and 21-25 us per
+// launched 63^2 step
+constexpr int kResidentAutoSteps = 32;
 
 bool resident_eligible(const Plan& pl) {
     const int NP = pl.np[0];
@@ -663,11 +668,12 @@ bool stream_capturing(hipStream_t s) {
 
 // The schedule a run takes: ETD_SCHEDULE_STAGES or ETD_SCHEDULE_RESIDENT, or
 // ETD_SCHEDULE_AUTO if a forced resident schedule cannot run here (capture).
-int resolve_schedule(const Plan& pl, const StageTimer& tm, hipStream_t s) {
+int resolve_schedule(const Plan& pl, const StageTimer& tm, int nsteps, hipStream_t s) {
     if (pl.schedule == ETD_SCHEDULE_STAGES || !resident_eligible(pl)) return ETD_SCHEDULE_STAGES;
     const bool capturing = stream_capturing(s);
     if (pl.schedule == ETD_SCHEDULE_RESIDENT) return capturing ? ETD_SCHEDULE_AUTO : ETD_SCHEDULE_RESIDENT;
-    if (capturing || tm.on || resident_tiles(pl) > kResidentAutoTiles) return ETD_SCHEDULE_STAGES;
+    if (capturing || tm.on || nsteps < kResidentAutoSteps || resident_tiles(pl) > kResidentAutoTiles)
+        return ETD_SCHEDULE_STAGES;
     return ETD_SCHEDULE_RESIDENT;
 }
 
@@ -720,7 +726,7 @@ etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int ns
     typedef typename M::elem T;
     if (w_out == nullptr && use_split2d(pl)) return run_steps_split2d<M, NC>(pl, tm, ws, t0, nsteps, s);
     if (w_out == nullptr) {
-        const int sch = resolve_schedule(pl, tm, s);
+        const int sch = resolve_schedule(pl, tm, nsteps, s);
         if (sch == ETD_SCHEDULE_AUTO)
             return fail(ETD_EUNSUPPORTED, "the resident schedule is one cooperative launch and cannot be captured");
         if (sch == ETD_SCHEDULE_RESIDENT) return run_steps_resident<M, NC>(pl, ws, t0, nsteps, s);

@@ -120,29 +120,34 @@ def test_resident_resumes_exactly(etd):
 
 
 def test_auto_schedule_capture_and_timing(etd):
-    """AUTO runs resident on the small grid, falls back to per-stage launches
-    under capture and while stage timing is on; a forced resident schedule
-    refuses capture."""
+    """AUTO runs resident on the small grid for calls of at least 32 steps,
+    and per-stage launches for shorter calls, under capture and while stage
+    timing is on; a forced resident schedule refuses capture.  All agree bit
+    for bit."""
     import torch
     p = W.Problem(dim=2, n=(63, 63), kappa=(0.01,), tau=0.01, reaction="fisher")
     u0 = W.u0_sine_noise(p, 5)
     st = etd.Stepper(p)
     assert st.schedule() == "resident"
     eager = st.field(u0)
-    st.advance(eager, 10)
+    st.advance(eager, 40)                       # resident
+    short = st.field(u0)
+    for _ in range(4):
+        st.advance(short, 10)                   # per-stage launches (calls under 32 steps)
+    assert np.array_equal(host(short), host(eager))
     # timing on: per-stage launches, so every stage is timed
     etd.etd_timing_enable(st.plan, 1)
     timed = st.field(u0)
-    st.advance(timed, 10)
+    st.advance(timed, 40)
     ms, counts = etd.etd_timing_read(st.plan)
     etd.etd_timing_enable(st.plan, 0)
-    assert list(counts)[0] == 10 and list(counts)[2] == 10
+    assert list(counts)[0] == 40 and list(counts)[2] == 40
     assert np.array_equal(host(timed), host(eager))
     # capture under AUTO: per-stage graph, replays equal the resident run
     s = torch.cuda.Stream()
     u = st.field(u0)
     torch.cuda.synchronize()
-    g = st.capture(u, 10, s)
+    g = st.capture(u, 40, s)
     for r in range(2):
         if r:
             u.copy_(st.field(u0))
@@ -153,7 +158,7 @@ def test_auto_schedule_capture_and_timing(etd):
     g.close()
     st.set_schedule("resident")
     with pytest.raises(etd.EtdError) as ei:
-        st.capture(st.field(u0), 10, s)
+        st.capture(st.field(u0), 40, s)
     assert ei.value.status == etd.ETD_EUNSUPPORTED
     torch.cuda.synchronize()
     st.close()

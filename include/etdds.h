@@ -234,18 +234,15 @@ etd_status etd_plan_autotune(etd_plan* plan, void* workspace_dev, void* stream);
  *    between stages.  Applies to grids whose directions share one padded
  *    extent of at most 128 points.  etd_advance returns ETD_EUNSUPPORTED on a
  *    stream that is capturing a graph; stage timing records nothing for it.
- *  - ETD_SCHEDULE_AUTO (default): RESIDENT where it applies, no stage has
- *    more than 16 tiles of 16 columns or lines (two-dimensional grids up to
- *    128 x 128 padded points) and the call has at least 32 steps (a
- *    cooperative launch costs more host time than a few launched steps), on
- *    a stream that is not capturing and with stage timing off; STAGES
- *    otherwise.
+ *    A cooperative launch costs tens of microseconds of host time, and on
+ *    small grids per-stage launches of one-block tiles are as fast, so it is
+ *    never chosen by AUTO.
+ *  - ETD_SCHEDULE_AUTO (default): STAGES.
  * etd_plan_set_schedule: ETD_EINVAL for an unknown value, ETD_EUNSUPPORTED for
  * RESIDENT on a plan it does not apply to (the plan is then unchanged).
  * etd_plan_schedule: the schedule (STAGES or RESIDENT) that etd_advance takes
- * for a call of at least 32 steps on a stream that is not capturing, with
- * stage timing off.  Tile shapes set
- * with etd_plan_set_tiles apply to the STAGES schedule only. */
+ * on a stream that is not capturing.  Tile shapes set with etd_plan_set_tiles
+ * apply to the STAGES schedule only. */
 typedef enum { ETD_SCHEDULE_AUTO = 0, ETD_SCHEDULE_STAGES = 1, ETD_SCHEDULE_RESIDENT = 2 } etd_schedule;
 etd_status etd_plan_set_schedule(etd_plan* plan, int schedule);
 etd_status etd_plan_schedule(const etd_plan* plan, int* schedule);

@@ -322,8 +322,7 @@ def etd_plan_set_schedule(plan, schedule):
 
 
 def etd_plan_schedule(plan):
-    """"stages" or "resident": the schedule etd_advance takes for calls of at least 32 steps
-    outside capture, timing off."""
+    """"stages" or "resident": the schedule etd_advance takes outside graph capture."""
     v = ctypes.c_int(-1)
     _check(lib().etd_plan_schedule(plan, ctypes.byref(v)))
     return {1: "stages", 2: "resident"}[v.value]

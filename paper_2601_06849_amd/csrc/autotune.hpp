@@ -106,15 +106,15 @@ etd_status autotune_plan_t(Plan& pl, char* ws, hipStream_t s) {
 }
 
 // Validate and resolve a tile request for one direction of a plan: (0, 0)
-// selects the default shape.
+// selects the default shape (`copies`: instances sharing each launch).
 template <typename M, int NC>
-etd_status resolve_tile(const Plan& pl, int d, TileShape t, TileShape& out) {
+etd_status resolve_tile(const Plan& pl, int d, TileShape t, TileShape& out, long copies) {
     typedef typename M::elem T;
     const int NP = pl.np[d];
     const long nlines = long(pl.np[1]) * pl.np[2];
     if (t.rb == 0 && t.cb == 0) {
         const long ncols16 = long(pl.np[0]) * pl.np[1] * pl.np[2] / NP / 16;
-        out = d == 0 ? default_x_for<M, NC>(NP, nlines) : default_outer_for<M, NC>(NP, ncols16);
+        out = d == 0 ? default_x_for<M, NC>(NP, nlines, copies) : default_outer_for<M, NC>(NP, ncols16, copies);
         return ETD_OK;
     }
     const bool ok = d == 0 ? x_shape_ok<T, NC>(NP, nlines, t) : outer_shape_ok<T, NC>(NP, t);

@@ -86,8 +86,8 @@ etd_status batch_dispatch_advance(Batch& B, void* const* u, double t0, int nstep
     return ops_for(B.precision).batch_advance(B, u, t0, nsteps, ws, s);
 }
 
-etd_status resolve_tile_any(const Plan& pl, int d, TileShape t, TileShape& out) {
-    return ops_for(pl.prob.precision).resolve_tile(pl, d, t, out);
+etd_status resolve_tile_any(const Plan& pl, int d, TileShape t, TileShape& out, long copies = 1) {
+    return ops_for(pl.prob.precision).resolve_tile(pl, d, t, out, copies);
 }
 
 etd_status batch_check(const Batch& B, void* const* u, int nsteps, const void* ws) {
@@ -308,11 +308,8 @@ etd_status etd_plan_set_schedule(etd_plan* plan, int schedule) {
 etd_status etd_plan_schedule(const etd_plan* plan, int* schedule) {
     if (!plan || !schedule) return fail(ETD_EINVAL, "NULL argument");
     const Plan& pl = plan->p;
-    int s = ETD_SCHEDULE_STAGES;
-    if (resident_eligible(pl) && (pl.schedule == ETD_SCHEDULE_RESIDENT ||
-                                  (pl.schedule == ETD_SCHEDULE_AUTO && resident_tiles(pl) <= kResidentAutoTiles)))
-        s = ETD_SCHEDULE_RESIDENT;
-    *schedule = s;
+    *schedule = pl.schedule == ETD_SCHEDULE_RESIDENT && resident_eligible(pl) ? ETD_SCHEDULE_RESIDENT
+                                                                               : ETD_SCHEDULE_STAGES;
     return ETD_OK;
 }
 
@@ -370,7 +367,7 @@ etd_status etd_batch_create(const etd_problem* probs, int count, etd_batch** out
     for (BatchGroup& G : B.groups) {
         const Plan& pl = B.plans[G.inst[0]];
         for (int d = 0; d < pl.dim; ++d) {
-            const etd_status st = resolve_tile_any(pl, d, TileShape{}, G.tile[d]);
+            const etd_status st = resolve_tile_any(pl, d, TileShape{}, G.tile[d], long(G.inst.size()));
             if (st != ETD_OK) {
                 delete b;
                 return st;

@@ -143,9 +143,17 @@ constexpr bool fp64_state_reduced() {
     return sizeof(typename M::elem) == 8 && sizeof(typename M::acc) == 4;
 }
 
+// A launch of at most kFewTiles one-block tiles leaves CUs idle with larger
+// tiles, so it takes one row block per wave over one block (every tile shape
+// gives the same result): at 63^2 FP64 the per-stage kernels take 11.4 (x)
+// and 8.9 us (y) with two-block tiles on two CUs.  `copies`: instances that
+// share the launch (a batch group).
+constexpr long kFewTiles = 256;
+
 template <typename M, int NC>
-TileShape default_outer_for(int NP, long ncols16) {
+TileShape default_outer_for(int NP, long ncols16, long copies = 1) {
     typedef typename M::elem T;
+    if (ncols16 * copies <= kFewTiles && outer_shape_ok<T, NC>(NP, TileShape{1, 1})) return TileShape{1, 1};
     if (fp64_state_reduced<M>() && outer_shape_ok<T, NC>(NP, TileShape{2, 1})) return TileShape{2, 1};
     if (M::SPLIT_B && NC == 1 && outer_shape_ok<T, NC>(NP, TileShape{4, 2})) return TileShape{4, 2};
     // FP32 products at NP = 256 with at least 1024 two-block tiles take four
@@ -157,8 +165,9 @@ TileShape default_outer_for(int NP, long ncols16) {
 }
 
 template <typename M, int NC>
-TileShape default_x_for(int NP, long nlines) {
+TileShape default_x_for(int NP, long nlines, long copies = 1) {
     typedef typename M::elem T;
+    if (nlines / 16 * copies <= kFewTiles && x_shape_ok<T, NC>(NP, nlines, TileShape{1, 1})) return TileShape{1, 1};
     if (fp64_state_reduced<M>()) {
         if (!M::SPLIT_B && x_shape_ok<T, NC>(NP, nlines, TileShape{2, 2})) return TileShape{2, 2};
         if (x_shape_ok<T, NC>(NP, nlines, TileShape{2, 1})) return TileShape{2, 1};
@@ -628,22 +637,17 @@ etd_status run_steps_split2d(const Plan& pl, StageTimer& tm, char* ws, double t0
     return ETD_OK;
 }
 
-// Resident schedule: every step of a run in one cooperative launch, for grids
-// whose directions share one padded extent of at most kResidentMaxNP points
-// (fused tiles of one row block per wave and one column or line block: NP/16
-// waves).  AUTO takes it when no stage has more than kResidentAutoTiles tiles
-// and a call has at least kResidentAutoSteps steps, outside graph capture and
-// stage timing.  Measured per step (FP64 Fisher-KPP,
-// whole-run calls): 31^2 13.5 -> 10.7 us, 63^2 21.3 -> 15.1 us, 127^2 48.5 ->
-// 34.9 us; but 31^3 (64 tiles) 21.1 -> 35.6 us and 63^3 (256 tiles) 33.7 ->
-// 108 us, since the grid-wide barrier's cost grows with the workgroup count.
+// Resident schedule (ETD_SCHEDULE_RESIDENT): every step of a run in one
+// cooperative launch, for grids whose directions share one padded extent of at
+// most kResidentMaxNP points (fused tiles of one row block per wave and one
+// column or line block: NP/16 waves).  AUTO does not take it: with one-block
+// tiles the per-stage launches are as fast on small grids (63^2 FP64, 100-step
+// calls: 15.2 us per step against 14.9 resident; 127^2: 32.8 against 35.1;
+// a graph of per-stage launches 14.3 us at 63^2), a cooperative launch costs
+// 40-180 us of host time, and the grid-wide barrier's cost grows with the
+// workgroup count (63^3: 25 against 105 us).
 constexpr int kResidentMaxNP = 128;
 constexpr int kResidentThreads = 512;
-constexpr long kResidentAutoTiles = 16;
-// ... and only for calls of at least this many steps: a cooperative launch
-// costs 40-180 us of host time, against 15 us per resident and 21-25 us per
-// launched 63^2 step
-constexpr int kResidentAutoSteps = 32;
 
 bool resident_eligible(const Plan& pl) {
     const int NP = pl.np[0];
@@ -653,14 +657,6 @@ bool resident_eligible(const Plan& pl) {
     return !use_split2d(pl);
 }
 
-// Tiles of the largest stage (one 16-column or 16-line block each).
-long resident_tiles(const Plan& pl) {
-    const long px = pl.np[0], py = pl.np[1], pz = pl.np[2];
-    long t = std::max(px / 16 * pz, py * pz / 16);   // y (middle or first) and x stages
-    if (pl.dim == 3) t = std::max(t, px * py / 16);    // z stage
-    return t;
-}
-
 bool stream_capturing(hipStream_t s) {
     hipStreamCaptureStatus c = hipStreamCaptureStatusNone;
     return hipStreamIsCapturing(s, &c) == hipSuccess && c != hipStreamCaptureStatusNone;
@@ -668,13 +664,9 @@ bool stream_capturing(hipStream_t s) {
 
 // The schedule a run takes: ETD_SCHEDULE_STAGES or ETD_SCHEDULE_RESIDENT, or
 // ETD_SCHEDULE_AUTO if a forced resident schedule cannot run here (capture).
-int resolve_schedule(const Plan& pl, const StageTimer& tm, int nsteps, hipStream_t s) {
-    if (pl.schedule == ETD_SCHEDULE_STAGES || !resident_eligible(pl)) return ETD_SCHEDULE_STAGES;
-    const bool capturing = stream_capturing(s);
-    if (pl.schedule == ETD_SCHEDULE_RESIDENT) return capturing ? ETD_SCHEDULE_AUTO : ETD_SCHEDULE_RESIDENT;
-    if (capturing || tm.on || nsteps < kResidentAutoSteps || resident_tiles(pl) > kResidentAutoTiles)
-        return ETD_SCHEDULE_STAGES;
-    return ETD_SCHEDULE_RESIDENT;
+int resolve_schedule(const Plan& pl, hipStream_t s) {
+    if (pl.schedule != ETD_SCHEDULE_RESIDENT || !resident_eligible(pl)) return ETD_SCHEDULE_STAGES;
+    return stream_capturing(s) ? ETD_SCHEDULE_AUTO : ETD_SCHEDULE_RESIDENT;
 }
 
 template <typename M, int NC>
@@ -726,7 +718,7 @@ etd_status run_steps(const Plan& pl, StageTimer& tm, char* ws, double t0, int ns
     typedef typename M::elem T;
     if (w_out == nullptr && use_split2d(pl)) return run_steps_split2d<M, NC>(pl, tm, ws, t0, nsteps, s);
     if (w_out == nullptr) {
-        const int sch = resolve_schedule(pl, tm, nsteps, s);
+        const int sch = resolve_schedule(pl, s);
         if (sch == ETD_SCHEDULE_AUTO)
             return fail(ETD_EUNSUPPORTED, "the resident schedule is one cooperative launch and cannot be captured");
         if (sch == ETD_SCHEDULE_RESIDENT) return run_steps_resident<M, NC>(pl, ws, t0, nsteps, s);

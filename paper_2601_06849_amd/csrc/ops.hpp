@@ -26,8 +26,8 @@ etd_status op_autotune(Plan& pl, char* ws, hipStream_t s) {
 }
 
 template <typename M>
-etd_status op_resolve_tile(const Plan& pl, int d, TileShape t, TileShape& out) {
-    return pl.nc == 1 ? resolve_tile<M, 1>(pl, d, t, out) : resolve_tile<M, 2>(pl, d, t, out);
+etd_status op_resolve_tile(const Plan& pl, int d, TileShape t, TileShape& out, long copies) {
+    return pl.nc == 1 ? resolve_tile<M, 1>(pl, d, t, out, copies) : resolve_tile<M, 2>(pl, d, t, out, copies);
 }
 
 template <typename M>

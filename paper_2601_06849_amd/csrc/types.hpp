@@ -74,8 +74,9 @@ struct PrecisionOps {
     etd_status (*adjoint)(const Plan& pl, StageTimer& tm, const void* u0, double t0, int nsteps, int segment,
                           const void* ubar_final, void* ubar0, double* grad, char* ws, char* aws, hipStream_t s);
     etd_status (*autotune)(Plan& pl, char* ws, hipStream_t s);
-    // validate a tile request for direction d ((0, 0): the default shape)
-    etd_status (*resolve_tile)(const Plan& pl, int d, TileShape t, TileShape& out);
+    // validate a tile request for direction d ((0, 0): the default shape for
+    // `copies` instances sharing each launch)
+    etd_status (*resolve_tile)(const Plan& pl, int d, TileShape t, TileShape& out, long copies);
     etd_status (*batch_advance)(Batch& B, void* const* u, double t0, int nsteps, char* ws, hipStream_t s);
     etd_status (*batch_autotune)(Batch& B, char* ws, hipStream_t s);
 };

@@ -272,19 +272,16 @@ def test_tile_shapes_host_validation(etd):
 
 def test_schedule_host_validation(etd):
     """The resident schedule (all steps in one cooperative launch) applies to
-    grids whose directions share one padded extent of at most 128; AUTO takes
-    it when no stage has more than 16 tiles of 16 columns or lines."""
-    cases = [((63, 63), "resident", True), ((64, 50), "resident", True), ((127, 120), "resident", True),
-             ((1, 1), "resident", True),
-             ((63, 63, 63), "stages", True), ((31, 20, 17), "stages", True),    # 256 and 64 tiles a stage
-             ((127, 127, 127), "stages", True),
-             ((63, 65), "stages", False), ((255, 255), "stages", False), ((63, 63, 80), "stages", False),
-             ((255, 255, 255), "stages", False)]
-    for n, auto, eligible in cases:
+    grids whose directions share one padded extent of at most 128; AUTO is
+    the per-stage schedule."""
+    cases = [((63, 63), True), ((64, 50), True), ((127, 120), True), ((1, 1), True), ((63, 63, 63), True),
+             ((31, 20, 17), True), ((127, 127, 127), True),
+             ((63, 65), False), ((255, 255), False), ((63, 63, 80), False), ((255, 255, 255), False)]
+    for n, eligible in cases:
         p = W.Problem(dim=len(n), n=n, kappa=(0.01,), tau=0.01, reaction="fisher")
         plan = etd.etd_plan_create(p)
         try:
-            assert etd.etd_plan_schedule(plan) == auto, n
+            assert etd.etd_plan_schedule(plan) == "stages", n
             etd.etd_plan_set_schedule(plan, "stages")
             assert etd.etd_plan_schedule(plan) == "stages"
             if eligible:
@@ -296,14 +293,41 @@ def test_schedule_host_validation(etd):
                 assert ei.value.status == etd.ETD_EUNSUPPORTED
                 assert etd.etd_plan_schedule(plan) == "stages"      # unchanged
             etd.etd_plan_set_schedule(plan, "auto")
-            assert etd.etd_plan_schedule(plan) == auto
+            assert etd.etd_plan_schedule(plan) == "stages"
             for bad in (-1, 3, 7):
                 with pytest.raises(etd.EtdError) as ei:
                     etd.etd_plan_set_schedule(plan, bad)
                 assert ei.value.status == etd.ETD_EINVAL
-            assert etd.etd_plan_schedule(plan) == auto
+            assert etd.etd_plan_schedule(plan) == "stages"
         finally:
             etd.etd_plan_destroy(plan)
+
+
+def test_small_grid_default_tiles(etd):
+    """A launch of at most 256 one-block tiles takes one row block per wave
+    over one block (the larger default tiles would leave CUs idle); a batch
+    group counts the tiles of all its instances."""
+    for n, prec in (((63, 63), "fp64"), ((255, 255), "fp64"), ((63, 63, 63), "fp32"), ((31, 31), "bf16x6"),
+                    ((63, 63), "fp64_fp32"), ((127, 63), "fp64_bf16x6")):
+        p = W.Problem(dim=len(n), n=n, kappa=(0.01,), tau=0.01, reaction="fisher", precision=prec)
+        plan = etd.etd_plan_create(p)
+        try:
+            assert etd.etd_plan_tiles(plan)[:len(n)] == [(1, 1)] * len(n), (n, prec)
+        finally:
+            etd.etd_plan_destroy(plan)
+    p = W.Problem(dim=3, n=(255, 255, 255), kappa=(0.01,), tau=0.01, reaction="fisher")
+    plan = etd.etd_plan_create(p)
+    try:
+        assert etd.etd_plan_tiles(plan) == [(1, 2), (1, 2), (1, 2)]
+    finally:
+        etd.etd_plan_destroy(plan)
+    # 300 instances of 63^2: 1200 tiles per stage launch, so the group keeps the larger tiles
+    probs = [W.Problem(dim=2, n=(63, 63), kappa=(0.01,), tau=0.01, reaction="fisher")] * 300
+    b = etd.etd_batch_create(probs)
+    try:
+        assert etd.etd_batch_tiles(b, 0)[:2] == [(1, 2), (1, 2)]
+    finally:
+        etd.etd_batch_destroy(b)
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -38,7 +38,7 @@ def host(t):
 def run(etd, p, u0, nsteps, schedule, t0=0.0, chunks=None):
     st = etd.Stepper(p)
     st.set_schedule(schedule)
-    assert st.schedule() == (schedule if schedule != "auto" else st.schedule())
+    assert st.schedule() == schedule
     u = st.field(u0)
     t = t0
     for k in (chunks or [nsteps]):
@@ -119,32 +119,37 @@ def test_resident_resumes_exactly(etd):
     assert np.array_equal(a, b)
 
 
-def test_auto_schedule_capture_and_timing(etd):
-    """AUTO runs resident on the small grid for calls of at least 32 steps,
-    and per-stage launches for shorter calls, under capture and while stage
-    timing is on; a forced resident schedule refuses capture.  All agree bit
-    for bit."""
+def test_resident_capture_and_timing(etd):
+    """AUTO is the per-stage schedule; a forced resident schedule refuses
+    graph capture and records no stage times, and all agree bit for bit."""
     import torch
     p = W.Problem(dim=2, n=(63, 63), kappa=(0.01,), tau=0.01, reaction="fisher")
     u0 = W.u0_sine_noise(p, 5)
     st = etd.Stepper(p)
+    assert st.schedule() == "stages"
+    st.set_schedule("resident")
     assert st.schedule() == "resident"
-    eager = st.field(u0)
-    st.advance(eager, 40)                       # resident
-    short = st.field(u0)
-    for _ in range(4):
-        st.advance(short, 10)                   # per-stage launches (calls under 32 steps)
-    assert np.array_equal(host(short), host(eager))
-    # timing on: per-stage launches, so every stage is timed
+    res = st.field(u0)
+    st.advance(res, 40)
+    # timing on: the resident launch is not a stage launch, so nothing is timed
     etd.etd_timing_enable(st.plan, 1)
     timed = st.field(u0)
     st.advance(timed, 40)
     ms, counts = etd.etd_timing_read(st.plan)
     etd.etd_timing_enable(st.plan, 0)
-    assert list(counts)[0] == 40 and list(counts)[2] == 40
-    assert np.array_equal(host(timed), host(eager))
-    # capture under AUTO: per-stage graph, replays equal the resident run
+    assert list(counts) == [0, 0, 0]
+    assert np.array_equal(host(timed), host(res))
     s = torch.cuda.Stream()
+    with pytest.raises(etd.EtdError) as ei:
+        st.capture(st.field(u0), 40, s)
+    assert ei.value.status == etd.ETD_EUNSUPPORTED
+    torch.cuda.synchronize()
+    # AUTO: per-stage launches, eagerly and from a graph, equal the resident run
+    st.set_schedule("auto")
+    eager = st.field(u0)
+    for _ in range(4):
+        st.advance(eager, 10)
+    assert np.array_equal(host(eager), host(res))
     u = st.field(u0)
     torch.cuda.synchronize()
     g = st.capture(u, 40, s)
@@ -154,11 +159,6 @@ def test_auto_schedule_capture_and_timing(etd):
             torch.cuda.synchronize()
         g.launch(s)
         s.synchronize()
-        assert np.array_equal(host(u), host(eager)), r
+        assert np.array_equal(host(u), host(res)), r
     g.close()
-    st.set_schedule("resident")
-    with pytest.raises(etd.EtdError) as ei:
-        st.capture(st.field(u0), 40, s)
-    assert ei.value.status == etd.ETD_EUNSUPPORTED
-    torch.cuda.synchronize()
     st.close()

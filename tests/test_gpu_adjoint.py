@@ -183,7 +183,7 @@ def fhn3d_target(oracle_mod, g):
     return _FHN3D_TARGET["t"]
 
 
-# relative bound per precision: FP64 at the benchmark spec's 1e-6; the reduced
+# relative bound per precision: FP64 at the 1e-6 gradient target; the reduced
 # modes at bounds derived from their rounding (see the test's docstring;
 # measured: FP64 <= 6.8e-8, FP64 state with FP32 products <= 1.3e-6, FP32
 # state <= 8.2e-6)

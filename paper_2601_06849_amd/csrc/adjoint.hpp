@@ -139,6 +139,41 @@ etd_status launch_xadj_k(const XAdjArgs& a, long nlines, hipStream_t s) {
 }
 #define XADJ_K(RB, MAXT, M, NC, SECOND, a, nl, s) launch_xadj_k<M, NC, RB, MAXT, SECOND>(a, nl, s)
 
+// The x adjoint of all components in one kernel (up to NP = 128, the shape
+// of one row block per wave, where its registers fit): two line blocks where
+// their four fields per component fit in LDS, else one; 0 beyond NP = 128 or
+// where not even one fits (the two kernels above then run).
+int adjoint_joint_cb(int NP, int nc, size_t elem) {
+    if (NP > 128) return 0;
+    if (x_lds_bytes(NP, 4 * nc, 2, elem) + kStaticLds <= kMaxLds) return 2;
+    if (x_lds_bytes(NP, 4 * nc, 1, elem) + kStaticLds <= kMaxLds) return 1;
+    return 0;
+}
+
+template <typename M, int NC, int RB, int CB, int MAXT>
+etd_status launch_xadj_joint_cb(const XAdjArgs& a, long nlines, hipStream_t s) {
+    typedef typename M::elem T;
+    const size_t lds = x_lds_bytes(a.NP, 4 * NC, CB, sizeof(T));
+    auto k = x_adjoint_joint<M, NC, RB, CB, MAXT>;
+    static size_t done = 0;
+    HIP_TRY(set_lds(k, lds, done), "joint adjoint x LDS attribute");
+    hipLaunchKernelGGL(k, dim3(unsigned(nlines / (16 * CB))), dim3(shape_threads(a.NP, RB)), lds, s, a);
+    HIP_TRY(hipGetLastError(), "joint adjoint x launch");
+    return ETD_OK;
+}
+
+template <typename M, int NC, int RB, int MAXT>
+etd_status launch_xadj_joint(const XAdjArgs& a, long nlines, hipStream_t s) {
+    if constexpr (RB == 1 && MAXT <= 512) {
+        if (adjoint_joint_cb(a.NP, NC, sizeof(typename M::elem)) == 2 && nlines % 32 == 0)
+            return launch_xadj_joint_cb<M, NC, RB, 2, MAXT>(a, nlines, s);
+        return launch_xadj_joint_cb<M, NC, RB, 1, MAXT>(a, nlines, s);
+    } else {
+        return fail(ETD_EUNSUPPORTED, "joint adjoint x kernel beyond 128 points");
+    }
+}
+#define XADJJ_K(RB, MAXT, M, NC, a, nl, s) launch_xadj_joint<M, NC, RB, MAXT>(a, nl, s)
+
 // Adjoint tiles hold four fields, so at small extents few workgroups fit per
 // CU: one row block per wave up to NP = 128 doubles their waves (the adjoint
 // kernels of a 127^3 two-component FP32 step: 0.335 -> 0.296 ms with the
@@ -261,9 +296,13 @@ etd_status adjoint_t(const Plan& pl, StageTimer& tm, const void* u0, double t0, 
             xa.tau = tau;
             xa.rxn = rxn_args(pl, ws, tn1);
             xa.grad = GradArgs{gtab, reinterpret_cast<double*>(aws + L.part[kPartXg]), 0, inv_dim};
-            TRY(ADJ_SHAPE(px, XADJ_K, M, NC, false, xa, long(py) * pz, s));
-            xa.grad.partial = reinterpret_cast<double*>(aws + L.part[kPartXw]);
-            TRY(ADJ_SHAPE(px, XADJ_K, M, NC, true, xa, long(py) * pz, s));
+            if (adjoint_joint_cb(px, NC, sizeof(T)) > 0) {
+                TRY(ADJ_SHAPE(px, XADJJ_K, M, NC, xa, long(py) * pz, s));
+            } else {
+                TRY(ADJ_SHAPE(px, XADJ_K, M, NC, false, xa, long(py) * pz, s));
+                xa.grad.partial = reinterpret_cast<double*>(aws + L.part[kPartXw]);
+                TRY(ADJ_SHAPE(px, XADJ_K, M, NC, true, xa, long(py) * pz, s));
+            }
             // outer directions
             OuterAdjArgs oa{};
             oa.diag_cstride = dcs;

@@ -338,6 +338,233 @@ __global__ __launch_bounds__(MAXT) void x_adjoint_w(XAdjArgs a) {
     add_partials<NC + 1>(gacc, a.grad.partial, grid_slot());
 }
 
+// x-direction adjoint of every component of 16*CB lines in one workgroup,
+// where the 4*NC fields fit in LDS: parts (a) and (b) above with g, Wbar and
+// the weights h kept on chip (no round trip through memory, and each P
+// fragment feeds the products of all components).  LDS: field f*NC + c of
+// component c, f = 0 (U+bar, then (q3 - 1/2) P U+bar, then Wbar, then
+// (q1 - 1) P Wbar), 1 (w, then tau (q2 - 1) P Wbar), 2 (v), 3 (d = f(W) - v).
+// The gradient partials go to the slots of part (a).
+template <typename M, int NC, int RB, int CB, int MAXT>
+__global__ __launch_bounds__(MAXT) void x_adjoint_joint(XAdjArgs a) {
+    typedef typename M::elem T;
+    typedef typename Vec4<T>::type T4;
+    typedef typename M::acc AT;
+    typedef typename Vec4<AT>::type A4;
+    typedef typename Vec16<T>::type TV;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int NL = 16 * CB;
+    constexpr int NF = 4 * NC;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* R = reinterpret_cast<T*>(smem_raw);
+    const int NP = a.NP;
+    const int RS = NP + 16 / int(sizeof(T));
+    const int AST = NL * RS;
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int li = lane & 15, lg = lane >> 4;
+    const long line0 = long(blockIdx.x) * NL;
+    const void* __restrict__ P = a.P;
+    const T tau = T(a.tau);
+    const int vpl = NP / VN;
+    const T* ubar = static_cast<const T*>(a.ubar);
+    const T* Wf = static_cast<const T*>(a.W);
+    const T* wf = static_cast<const T*>(a.w);
+    const T* vf = static_cast<const T*>(a.v);
+#pragma unroll 2
+    for (int v = tid; v < NL * vpl; v += blockDim.x) {
+        const int j = v / vpl, x = (v - j * vpl) * VN;
+        const long gi = line0 * NP + long(v) * VN;
+        const long line = line0 + j;
+        const int y = int(line % a.npy), z = int(line / a.npy);
+        TV Wk[NC], vv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            Wk[c] = *reinterpret_cast<const TV*>(Wf + c * a.sc + gi);
+            vv[c] = *reinterpret_cast<const TV*>(vf + c * a.sc + gi);
+            *reinterpret_cast<TV*>(R + c * AST + j * RS + x) = *reinterpret_cast<const TV*>(ubar + c * a.sc + gi);
+            *reinterpret_cast<TV*>(R + (NC + c) * AST + j * RS + x) = *reinterpret_cast<const TV*>(wf + c * a.sc + gi);
+            *reinterpret_cast<TV*>(R + (2 * NC + c) * AST + j * RS + x) = vv[c];
+        }
+        TV d[NC];
+#pragma unroll
+        for (int t = 0; t < VN; ++t) {
+            T Wv[NC], F[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) Wv[c] = Wk[c][t];
+            react<T, NC>(a.rxn, Wv, F, x + t, y, z);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) d[c][t] = F[c] - vv[c][t];
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) *reinterpret_cast<TV*>(R + (3 * NC + c) * AST + j * RS + x) = d[c];
+    }
+    __syncthreads();
+    const int rb0 = RB * w;
+    auto bfrag = [&](int qq, int k0) {
+        return lds_vec<T, M::KL>(R + (qq / CB) * AST + ((qq % CB) * 16 + li) * RS + k0);
+    };
+    auto at = [&](int f, int b, int r, int e) -> T& {
+        return R[f * AST + (b * 16 + li) * RS + 16 * (rb0 + r) + M::row(lg, e)];
+    };
+    auto wt = [&](int c) {
+        return a.grad.table + c * (3L * kGradSlots * kMaxPadded) + (long(a.grad.dir) * kGradSlots) * kMaxPadded;
+    };
+    auto dslot = [&](int c, int slot) {
+        return static_cast<const T*>(a.diag) + c * a.diag_cstride + slot * a.diag_sstride;
+    };
+    double gacc[NC + 1];
+#pragma unroll
+    for (int k = 0; k <= NC; ++k) gacc[k] = 0.0;
+
+    // ---- S1 = P U+bar, Sw = P w, Sv = P v, Sd = P d of every component ----
+    T4 ub[RB][NC][CB], h[RB][NC][CB];
+    {
+        A4 acc[RB][NF * CB];
+        zero<AT, RB, NF * CB>(acc);
+        gemm<M, RB, NF * CB>(P, NP, rb0, li, lg, acc, bfrag);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double* wc = wt(c);
+#pragma unroll
+            for (int b = 0; b < CB; ++b)
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int k = 16 * (rb0 + r) + M::row(lg, e);
+                        ub[r][c][b][e] = at(c, b, r, e);
+                        const double t3 = double(acc[r][c * CB + b][e]) * double(acc[r][(3 * NC + c) * CB + b][e]) *
+                                          wc[kGradRho3 * kMaxPadded + k];
+                        gacc[c] += t3 * wc[kGradMu * kMaxPadded + k];
+                        gacc[NC] += t3 * a.grad.inv_dim;
+                        h[r][c][b][e] = T(double(acc[r][(NC + c) * CB + b][e]) * wc[kGradRho1 * kMaxPadded + k] +
+                                          double(acc[r][(2 * NC + c) * CB + b][e]) * wc[kGradRho2 * kMaxPadded + k]);
+                    }
+        }
+        __syncthreads();
+        // (q3 - 1/2) S1 over U+bar
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const T* d3 = dslot(c, 2);
+#pragma unroll
+            for (int b = 0; b < CB; ++b)
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        at(c, b, r, e) = d3[16 * (rb0 + r) + M::row(lg, e)] * acc[r][c * CB + b][e];
+        }
+    }
+    __syncthreads();
+
+    // ---- g = tau (U+bar / 2 + P ((q3 - 1/2) S1)); Wbar = U+bar + J(W)^T g ----
+    T4 wb[RB][NC][CB], g[RB][NC][CB];
+    {
+        A4 acc[RB][NC * CB];
+        zero<AT, RB, NC * CB>(acc);
+        gemm<M, RB, NC * CB>(P, NP, rb0, li, lg, acc, bfrag);
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const long line = line0 + 16 * b + li;
+            const int y = int(line % a.npy), z = int(line / a.npy);
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int x = 16 * (rb0 + r) + M::row(lg, e);
+                    T Wv[NC], gg[NC], jt[NC];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        gg[c] = tau * (T(0.5) * ub[r][c][b][e] + acc[r][c * CB + b][e]);
+                        g[r][c][b][e] = gg[c];
+                        Wv[c] = Wf[c * a.sc + line * NP + x];
+                    }
+                    if (a.rxn.kind == ETD_RXN_AC_MMS) {   // psi(t_{n+1}) depends on kappa and q
+                        const double ue = ac_ue(a.rxn, x, y, z) * double(gg[0]);
+                        gacc[0] += a.rxn.ac_mu * ue;
+                        gacc[NC] += ue;
+                    }
+                    react_jt<T, NC>(a.rxn, Wv, gg, jt);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) wb[r][c][b][e] = ub[r][c][b][e] + jt[c];
+                }
+        }
+    }
+    __syncthreads();   // every wave has read (q3 - 1/2) S1
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int b = 0; b < CB; ++b)
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) at(c, b, r, e) = wb[r][c][b][e];
+    __syncthreads();
+
+    // ---- S2 = P Wbar; gradient terms against h; scaled coefficients ----
+    {
+        A4 acc[RB][NC * CB];
+        zero<AT, RB, NC * CB>(acc);
+        gemm<M, RB, NC * CB>(P, NP, rb0, li, lg, acc, bfrag);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double* wc = wt(c);
+#pragma unroll
+            for (int b = 0; b < CB; ++b)
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int k = 16 * (rb0 + r) + M::row(lg, e);
+                        const double t = double(acc[r][c * CB + b][e]) * double(h[r][c][b][e]);
+                        gacc[c] += t * wc[kGradMu * kMaxPadded + k];
+                        gacc[NC] += t * a.grad.inv_dim;
+                    }
+        }
+        __syncthreads();   // every wave has read Wbar
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const T* d1 = dslot(c, 0);
+            const T* d2 = dslot(c, 1);
+#pragma unroll
+            for (int b = 0; b < CB; ++b)
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int k = 16 * (rb0 + r) + M::row(lg, e);
+                        at(c, b, r, e) = d1[k] * acc[r][c * CB + b][e];        // (q1 - 1) S2
+                        at(NC + c, b, r, e) = d2[k] * acc[r][c * CB + b][e];   // tau (q2 - 1) S2
+                    }
+        }
+    }
+    __syncthreads();
+
+    // ---- wbar = Wbar + P ((q1 - 1) S2); vbar = -g + tau Wbar + P (tau (q2 - 1) S2) ----
+    A4 acc[RB][2 * NC * CB];
+    zero<AT, RB, 2 * NC * CB>(acc);
+    gemm<M, RB, 2 * NC * CB>(P, NP, rb0, li, lg, acc, bfrag);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const long o = c * a.sc + (line0 + 16 * b + li) * NP + 16 * rb0;
+            T* __restrict__ ow = static_cast<T*>(a.wbar) + o;
+            T* __restrict__ ov = static_cast<T*>(a.vbar) + o;
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int x = 16 * r + M::row(lg, e);
+                    ow[x] = wb[r][c][b][e] + acc[r][c * CB + b][e];
+                    ov[x] = -g[r][c][b][e] + tau * wb[r][c][b][e] + acc[r][(NC + c) * CB + b][e];
+                }
+        }
+    add_partials<NC + 1>(gacc, a.grad.partial, grid_slot());
+}
+
 struct OuterAdjArgs {
     const void* a0;       // adjoint inputs (two fields, all components)
     const void* a1;

@@ -141,11 +141,13 @@ etd_status launch_xadj_k(const XAdjArgs& a, long nlines, hipStream_t s) {
 
 // The x adjoint of all components in one kernel (up to NP = 128, the shape
 // of one row block per wave, where its registers fit): two line blocks where
-// their four fields per component fit in LDS, else one; 0 beyond NP = 128 or
-// where not even one fits (the two kernels above then run).
+// the four fields per component fit in LDS (not for two FP64-state
+// components, whose two-block tiles would spill), else one; 0 beyond NP =
+// 128 or where not even one fits (the two kernels above then run).  (A joint
+// outer adjoint measured no faster: 0.421 -> 0.425 ms per step.)
 int adjoint_joint_cb(int NP, int nc, size_t elem) {
     if (NP > 128) return 0;
-    if (x_lds_bytes(NP, 4 * nc, 2, elem) + kStaticLds <= kMaxLds) return 2;
+    if (!(elem == 8 && nc == 2) && x_lds_bytes(NP, 4 * nc, 2, elem) + kStaticLds <= kMaxLds) return 2;
     if (x_lds_bytes(NP, 4 * nc, 1, elem) + kStaticLds <= kMaxLds) return 1;
     return 0;
 }

@@ -30,6 +30,9 @@
  *    host before anything is enqueued and leave all buffers untouched.  HIP
  *    launch errors return ETD_EHIP.  etd_last_error() gives a thread-local
  *    message for the most recent failure.
+ *  - Calls on different plans or batches may run on different host threads
+ *    at once (the library's per-kernel launch caches are thread-safe); calls
+ *    on one plan or batch must not overlap.
  */
 #ifndef ETDDS_H
 #define ETDDS_H

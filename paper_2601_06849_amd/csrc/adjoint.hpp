@@ -121,7 +121,7 @@ etd_status launch_xadj_cb(const XAdjArgs& a, long nlines, hipStream_t s) {
     typedef typename M::elem T;
     const size_t lds = x_lds_bytes(a.NP, SECOND ? 2 : 4, CB, sizeof(T));
     auto k = SECOND ? x_adjoint_w<M, NC, RB, CB, MAXT> : x_adjoint_g<M, NC, RB, CB, MAXT>;
-    static size_t done = 0;
+    static std::atomic<size_t> done{0};
     HIP_TRY(set_lds(k, lds, done), "adjoint x LDS attribute");
     hipLaunchKernelGGL(k, dim3(unsigned(nlines / (16 * CB)), unsigned(NC)), dim3(shape_threads(a.NP, RB)), lds, s,
                        a);
@@ -157,7 +157,7 @@ etd_status launch_xadj_joint_cb(const XAdjArgs& a, long nlines, hipStream_t s) {
     typedef typename M::elem T;
     const size_t lds = x_lds_bytes(a.NP, 4 * NC, CB, sizeof(T));
     auto k = x_adjoint_joint<M, NC, RB, CB, MAXT>;
-    static size_t done = 0;
+    static std::atomic<size_t> done{0};
     HIP_TRY(set_lds(k, lds, done), "joint adjoint x LDS attribute");
     hipLaunchKernelGGL(k, dim3(unsigned(nlines / (16 * CB))), dim3(shape_threads(a.NP, RB)), lds, s, a);
     HIP_TRY(hipGetLastError(), "joint adjoint x launch");
@@ -187,7 +187,7 @@ etd_status launch_oadj_cb(OuterAdjArgs a, long nblocks, hipStream_t s) {
     typedef typename M::elem T;
     const size_t lds = outer_lds_bytes(a.NP, 4, CB, sizeof(T));
     auto k = outer_adjoint<M, NC, FIRST, RB, CB, MAXT>;
-    static size_t done = 0;
+    static std::atomic<size_t> done{0};
     HIP_TRY(set_lds(k, lds, done), "adjoint outer LDS attribute");
     a.ncb /= CB;
     hipLaunchKernelGGL(k, dim3(unsigned(nblocks / CB), unsigned(NC)), dim3(shape_threads(a.NP, RB)), lds, s, a);

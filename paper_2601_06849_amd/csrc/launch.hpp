@@ -53,13 +53,19 @@ RxnArgs rxn_args(const Plan& pl, const char* ws, double t) {
 }
 
 // Raise a kernel's dynamic-LDS limit once per instantiation (the attribute
-// persists for the process).
+// persists for the process).  `done` is the largest limit set so far; host
+// threads that launch the same kernel at once may both set it, and it only
+// grows.
 template <typename K>
-hipError_t set_lds(K kernel, size_t bytes, size_t& done) {
-    if (bytes <= done) return hipSuccess;
+hipError_t set_lds(K kernel, size_t bytes, std::atomic<size_t>& done) {
+    if (bytes <= done.load(std::memory_order_acquire)) return hipSuccess;
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
-    if (e == hipSuccess) done = bytes;
+    if (e == hipSuccess) {
+        size_t cur = done.load(std::memory_order_relaxed);
+        while (cur < bytes && !done.compare_exchange_weak(cur, bytes, std::memory_order_release)) {
+        }
+    }
     return e;
 }
 
@@ -200,15 +206,23 @@ long resident_groups(K kernel, int threads, size_t lds) {
 }
 
 struct GridCache {
+    std::mutex m;
     size_t lds = 0;
     long resident = 0;
+    // resident workgroups for `l` bytes of LDS (0 if the query failed)
     template <typename K>
-    long grid(K kernel, int threads, size_t l, long ntiles) {
+    long resident_for(K kernel, int threads, size_t l) {
+        std::lock_guard<std::mutex> lock(m);
         if (l != lds || resident == 0) {
             resident = resident_groups(kernel, threads, l);
             lds = l;
         }
-        return resident > 0 ? std::max(1L, std::min(ntiles, resident)) : ntiles;
+        return resident;
+    }
+    template <typename K>
+    long grid(K kernel, int threads, size_t l, long ntiles) {
+        const long r = resident_for(kernel, threads, l);
+        return r > 0 ? std::max(1L, std::min(ntiles, r)) : ntiles;
     }
 };
 
@@ -217,7 +231,7 @@ etd_status launch_outer_k(const OuterArgs& a, long ntiles, hipStream_t s) {
     typedef typename M::elem T;
     const size_t lds = outer_lds_bytes(a.NP, 2 * NC, CB, sizeof(T));
     auto k = outer_stage<M, NC, FIRST, RB, CB, MAXT>;
-    static size_t done = 0;
+    static std::atomic<size_t> done{0};
     HIP_TRY(set_lds(k, lds, done), "outer stage LDS attribute");
     hipLaunchKernelGGL(k, dim3(unsigned(ntiles)), dim3(shape_threads(a.NP, RB)), lds, s, a);
     HIP_TRY(hipGetLastError(), "outer stage launch");
@@ -231,7 +245,7 @@ etd_status launch_outer_group_k(const Group<OuterArgs>& g, int NP, hipStream_t s
     typedef typename M::elem T;
     const size_t lds = outer_lds_bytes(NP, 2 * NC, CB, sizeof(T));
     auto k = outer_group<M, NC, FIRST, RB, CB, MAXT>;
-    static size_t done = 0;
+    static std::atomic<size_t> done{0};
     static GridCache gc;
     HIP_TRY(set_lds(k, lds, done), "grouped outer stage LDS attribute");
     const int thr = shape_threads(NP, RB);
@@ -313,7 +327,7 @@ etd_status launch_x_k(const XArgs& a, long nlines, hipStream_t s) {
     typedef typename M::elem T;
     const size_t lds = x_lds_bytes(a.NP, 2 * NC, CB, sizeof(T));
     auto k = x_stage<M, NC, RB, CB, MAXT>;
-    static size_t done = 0;
+    static std::atomic<size_t> done{0};
     HIP_TRY(set_lds(k, lds, done), "x stage LDS attribute");
     hipLaunchKernelGGL(k, dim3(unsigned(nlines / (16 * CB))), dim3(shape_threads(a.NP, RB)), lds, s, a);
     HIP_TRY(hipGetLastError(), "x stage launch");
@@ -325,7 +339,7 @@ etd_status launch_x_group_k(const Group<XArgs>& g, int NP, hipStream_t s) {
     typedef typename M::elem T;
     const size_t lds = x_lds_bytes(NP, 2 * NC, CB, sizeof(T));
     auto k = x_group<M, NC, RB, CB, MAXT>;
-    static size_t done = 0;
+    static std::atomic<size_t> done{0};
     static GridCache gc;
     HIP_TRY(set_lds(k, lds, done), "grouped x stage LDS attribute");
     const int thr = shape_threads(NP, RB);
@@ -388,7 +402,7 @@ etd_status launch_xsplit_k(const XSplitArgs& a, long nlines, hipStream_t s) {
     typedef typename M::elem T;
     const size_t lds = x_lds_bytes(a.NP, 2, 1, sizeof(T));
     auto k = SECOND ? x_stage_u<M, RB, MAXT> : x_stage_w<M, RB, MAXT>;
-    static size_t done = 0;
+    static std::atomic<size_t> done{0};
     HIP_TRY(set_lds(k, lds, done), "split x stage LDS attribute");
     hipLaunchKernelGGL(k, dim3(unsigned(nlines / 16)), dim3(tile_threads(a.NP)), lds, s, a);
     HIP_TRY(hipGetLastError(), "split x stage launch");
@@ -565,7 +579,7 @@ etd_status launch_split_k(const SplitArgs& a, long ncols, hipStream_t s) {
     if (a.NP % (BK * KS) != 0) return fail(ETD_EINVAL, "2-D product chunks do not divide the padded extent");
     const size_t lds = split_lds_bytes(SplitShape<KIND, NC>::NARR, BK, KS, sizeof(T));
     auto k = split_product<M, NC, KIND, NW, BK, KS>;
-    static size_t done = 0;
+    static std::atomic<size_t> done{0};
     HIP_TRY(set_lds(k, lds, done), "2-D product LDS attribute");
     hipLaunchKernelGGL(k, dim3(unsigned(a.NP / (16 * NW) * (ncols / 16))), dim3(64 * NW * KS), lds, s, a);
     HIP_TRY(hipGetLastError(), "2-D product launch");
@@ -692,19 +706,20 @@ etd_status run_steps_resident(const Plan& pl, char* ws, double t0, int nsteps, h
     const size_t lds = std::max(outer_lds_bytes(NP, 2 * NC, 1, sizeof(T)), x_lds_bytes(NP, 2 * NC, 1, sizeof(T)));
     const int thr = shape_threads(NP, 1);
     auto k = resident_steps<M, NC, kResidentThreads>;
-    static size_t done = 0;
+    static std::atomic<size_t> done{0};
     static GridCache gc;
-    static int coop = -1;
-    if (coop < 0) {
+    static std::atomic<int> coop{-1};
+    if (coop.load() < 0) {
         int dev = 0, c = 0;
         HIP_TRY(hipGetDevice(&dev), "device query");
         HIP_TRY(hipDeviceGetAttribute(&c, hipDeviceAttributeCooperativeLaunch, dev), "cooperative launch query");
-        coop = c;
+        coop.store(c);
     }
-    if (!coop) return fail(ETD_EUNSUPPORTED, "the device does not support cooperative launches");
+    if (!coop.load()) return fail(ETD_EUNSUPPORTED, "the device does not support cooperative launches");
     HIP_TRY(set_lds(k, lds, done), "resident schedule LDS attribute");
-    const long grid = gc.grid(k, thr, lds, ntiles);
-    if (gc.resident < 1) return fail(ETD_EHIP, "resident schedule: occupancy query failed");
+    const long cap = gc.resident_for(k, thr, lds);
+    if (cap < 1) return fail(ETD_EHIP, "resident schedule: occupancy query failed");
+    const long grid = std::max(1L, std::min(ntiles, cap));
     void* args[] = {&a};
     HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k), dim3(unsigned(grid)), dim3(thr), args,
                                        unsigned(lds), s),

@@ -212,8 +212,10 @@ etd_status etd_timing_read(etd_plan* plan, double ms[3], long long counts[3]);
  * direction d (0 = x, 1 = y, 2 = z), tiles[2d] = 16-row blocks of each product
  * per wave and tiles[2d+1] = 16-column (outer stages) or 16-line (x stage)
  * blocks per workgroup; zeros for directions beyond dim.  Rows per wave are
- * 1, 2 or 4, and 8 (with one block) for FP32-state precisions; a tile has
- * NP / (16 rows) waves, at most 16.
+ * 1, 2 or 4, and 8 for FP32-state precisions: with one block, or, in the x
+ * direction of one-component systems whose lines are too long for a
+ * two-array tile of two blocks (from 640 padded points on), with two blocks
+ * in a tile that holds one array; a tile has NP / (16 rows) waves, at most 16.
  * etd_plan_tiles reports the shapes in use.  etd_plan_set_tiles selects them
  * ((0, 0) restores the built-in default of a direction); ETD_EUNSUPPORTED if a
  * shape is not valid there (wave count, LDS, line count), leaving the plan

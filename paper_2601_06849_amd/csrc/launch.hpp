@@ -110,6 +110,11 @@ bool outer_shape_ok(int NP, TileShape t) {
 template <typename T, int NC>
 bool x_shape_ok(int NP, long nlines, TileShape t) {
     if (!shape_rows_ok<T>(NP, t.rb)) return false;
+    // eight row blocks over two line blocks: the one-array tile of an FP32
+    // state, for lines whose two-array two-block tile exceeds the LDS
+    if (t.rb == 8 && t.cb == 2)
+        return sizeof(T) == 4 && NC == 1 && nlines % 32 == 0 && x_lds_bytes(NP, 2, 2, sizeof(T)) > kMaxLds &&
+               x_lds_bytes(NP, 1, 2, sizeof(T)) <= kMaxLds;
     if (t.cb == 2 || t.cb == 4) {
         if (t.rb >= 2 && shape_threads(NP, t.rb) > 512) return false;
         if ((t.rb == 4 && (t.cb == 4 || sizeof(T) != 4)) || t.rb == 8) return false;
@@ -174,6 +179,10 @@ template <typename M, int NC>
 TileShape default_x_for(int NP, long nlines, long copies = 1) {
     typedef typename M::elem T;
     if (nlines / 16 * copies <= kFewTiles && x_shape_ok<T, NC>(NP, nlines, TileShape{1, 1})) return TileShape{1, 1};
+    // lines too long for a two-array tile of two blocks: the one-array tile
+    // (1024-point FP32 x stage 2.07 -> 1.48 ms against four row blocks over
+    // one block; the 256-instance batch 16.7 -> 14.9 ms per step)
+    if (!M::SPLIT_B && x_shape_ok<T, NC>(NP, nlines, TileShape{8, 2})) return TileShape{8, 2};
     if (fp64_state_reduced<M>()) {
         if (!M::SPLIT_B && x_shape_ok<T, NC>(NP, nlines, TileShape{2, 2})) return TileShape{2, 2};
         if (x_shape_ok<T, NC>(NP, nlines, TileShape{2, 1})) return TileShape{2, 1};
@@ -325,7 +334,7 @@ etd_status launch_outer(OuterArgs a, long ncols16, TileShape t, hipStream_t s) {
 template <typename M, int NC, int RB, int CB, int MAXT>
 etd_status launch_x_k(const XArgs& a, long nlines, hipStream_t s) {
     typedef typename M::elem T;
-    const size_t lds = x_lds_bytes(a.NP, 2 * NC, CB, sizeof(T));
+    const size_t lds = x_lds_bytes(a.NP, x_one_array<M, NC, RB, CB>() ? 1 : 2 * NC, CB, sizeof(T));
     auto k = x_stage<M, NC, RB, CB, MAXT>;
     static std::atomic<size_t> done{0};
     HIP_TRY(set_lds(k, lds, done), "x stage LDS attribute");
@@ -337,7 +346,7 @@ etd_status launch_x_k(const XArgs& a, long nlines, hipStream_t s) {
 template <typename M, int NC, int RB, int CB, int MAXT>
 etd_status launch_x_group_k(const Group<XArgs>& g, int NP, hipStream_t s) {
     typedef typename M::elem T;
-    const size_t lds = x_lds_bytes(NP, 2 * NC, CB, sizeof(T));
+    const size_t lds = x_lds_bytes(NP, x_one_array<M, NC, RB, CB>() ? 1 : 2 * NC, CB, sizeof(T));
     auto k = x_group<M, NC, RB, CB, MAXT>;
     static std::atomic<size_t> done{0};
     static GridCache gc;
@@ -352,9 +361,16 @@ template <typename T, int NC, typename L>
 etd_status x_by_shape(int NP, TileShape t, L&& launch) {
     const bool small = shape_threads(NP, t.rb) <= 512;
     if (t.rb == 8) {
-        if constexpr (sizeof(T) == 4)
+        if constexpr (sizeof(T) == 4) {
+            if (t.cb == 2) {
+                if constexpr (NC == 1)
+                    return launch(std::integral_constant<int, 8>{}, std::integral_constant<int, 2>{},
+                                  std::integral_constant<int, 512>{});
+                return fail(ETD_EUNSUPPORTED, "tile shape not available for this system");
+            }
             return launch(std::integral_constant<int, 8>{}, std::integral_constant<int, 1>{},
                           std::integral_constant<int, 512>{});
+        }
         return fail(ETD_EUNSUPPORTED, "tile shape not available at this precision");
     }
     if (t.rb == 1) {

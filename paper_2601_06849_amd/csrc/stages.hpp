@@ -488,13 +488,151 @@ __device__ __forceinline__ void x_compute(const XArgs& a, long tile) {
     }
 }
 
+// x stage of one component over long lines whose two-array tile exceeds the
+// LDS: ONE array of 16*CB lines, so twice the lines of the two-array tile and
+// half the reads of P per line.  The first phase takes P w3 and P w4 in two
+// passes (w4 restaged over w3); the epilogue reads w3 and w4 at the wave's
+// rows from memory (the lines were just staged, so from L2), and V = W +
+// tau d/2 waits in the output lines.  Otherwise the same operations in the
+// same order as x_compute.
+template <typename M, int RB, int CB>
+__device__ __forceinline__ void x_tile_one_array(const XArgs& a, long tile) {
+    typedef typename M::elem T;
+    typedef typename Vec4<T>::type T4;
+    typedef typename M::acc AT;
+    typedef typename Vec4<AT>::type A4;
+    typedef typename Vec16<T>::type TV;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int NL = 16 * CB;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* R = reinterpret_cast<T*>(smem_raw);
+    const int NP = a.NP;
+    const int RS = NP + 16 / int(sizeof(T));
+    const int tid = tile_tid();
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int li = lane & 15, lg = lane >> 4;
+    const long line0 = tile * NL;
+    const void* __restrict__ P = a.P;
+    const T tau = T(a.tau);
+    const int rb0 = RB * w;
+    const T* __restrict__ w3 = static_cast<const T*>(a.w3);
+    const T* __restrict__ w4 = static_cast<const T*>(a.w4);
+    const T* __restrict__ dg = static_cast<const T*>(a.diag);
+    auto stage = [&](const T* __restrict__ f) {
+        const int vpl = NP / VN;
+        for (int v = tid; v < NL * vpl; v += blockDim.x) {
+            const int j = v / vpl, x = (v - j * vpl) * VN;
+            *reinterpret_cast<TV*>(R + j * RS + x) =
+                __builtin_nontemporal_load(reinterpret_cast<const TV*>(f + line0 * NP + long(v) * VN));
+        }
+    };
+    auto bfrag = [&](int qq, int k0) { return lds_vec<T, M::KL>(R + (li + 16 * qq) * RS + k0); };
+    auto at = [&](int cb, int r, int e) -> T& { return R[(li + 16 * cb) * RS + 16 * (rb0 + r) + M::row(lg, e)]; };
+
+    // ---- b1 = P w3, b2 = P w4 (two passes over the one array) ----
+    stage(w3);
+    __syncthreads();
+    A4 b1[RB][CB];
+    zero<AT, RB, CB>(b1);
+    gemm<M, RB, CB>(P, NP, rb0, li, lg, b1, bfrag);
+    __syncthreads();
+    stage(w4);
+    __syncthreads();
+    A4 acc[RB][CB];
+    zero<AT, RB, CB>(acc);
+    gemm<M, RB, CB>(P, NP, rb0, li, lg, acc, bfrag);
+    __syncthreads();
+    // ---- c = (q1 - 1) b1 + tau (q2 - 1) b2 ----
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const T* d1 = dg + 16 * (rb0 + r);
+        const T* d2 = d1 + a.diag_sstride;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = M::row(lg, e);
+                at(cb, r, e) = d1[k] * b1[r][cb][e] + d2[k] * acc[r][cb][e];
+            }
+    }
+    __syncthreads();
+
+    // ---- W = w3 + tau w4 + P c; d = f(W) - w4; V = W + tau d/2 ----
+    zero<AT, RB, CB>(acc);
+    gemm<M, RB, CB>(P, NP, rb0, li, lg, acc, bfrag);
+    __syncthreads();   // every wave has read c
+    // V = W + tau d/2 goes to the output lines (this tile's own) until the
+    // last product adds tau P e to it: registers are what limits this tile
+    T* __restrict__ out = static_cast<T*>(a.out);
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const long line = line0 + li + 16 * cb;
+        const int ly = int(line % a.npy), lz = int(line / a.npy);
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = 16 * (rb0 + r) + M::row(lg, e);
+                const T w3v = w3[line * NP + x], w4v = w4[line * NP + x];
+                T Wv[1], F[1];
+                Wv[0] = w3v + tau * w4v + acc[r][cb][e];
+                react<T, 1>(a.rxn, Wv, F, x, ly, lz);
+                if (a.Wout) static_cast<T*>(a.Wout)[line * NP + x] = Wv[0];
+                const T d = F[0] - w4v;
+                at(cb, r, e) = d;
+                out[line * NP + x] = Wv[0] + T(0.5) * tau * d;
+            }
+    }
+    zero<AT, RB, CB>(acc);
+    __syncthreads();
+
+    // ---- e = (q3 - 1/2) .* (P d) ----
+    gemm<M, RB, CB>(P, NP, rb0, li, lg, acc, bfrag);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const T* d3 = dg + 2 * a.diag_sstride + 16 * (rb0 + r);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) at(cb, r, e) = d3[M::row(lg, e)] * acc[r][cb][e];
+    }
+    zero<AT, RB, CB>(acc);
+    __syncthreads();
+
+    // ---- U+ = V + tau P e ----
+    gemm<M, RB, CB>(P, NP, rb0, li, lg, acc, bfrag);
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const long line = line0 + li + 16 * cb;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            T* o = out + line * NP + 16 * (rb0 + r);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[M::row(lg, e)] = o[M::row(lg, e)] + tau * acc[r][cb][e];
+        }
+    }
+}
+
+// Tiles of eight row blocks per wave over two line blocks (FP32 states, one
+// component) hold one array: x_tile_one_array.
+template <typename M, int NC, int RB, int CB>
+constexpr bool x_one_array() {
+    return NC == 1 && RB == 8 && CB == 2 && sizeof(typename M::elem) == 4;
+}
+
 template <typename M, int NC, int RB, int CB>
 __device__ __forceinline__ void x_tile(const XArgs& a, long tile) {
-    XRegs<M, NC, RB, CB> g;
-    x_load<M, NC, RB, CB>(a, tile, g);
-    x_store<M, NC, RB, CB>(a, g);
-    __syncthreads();
-    x_compute<M, NC, RB, CB>(a, tile);
+    if constexpr (x_one_array<M, NC, RB, CB>()) {
+        x_tile_one_array<M, RB, CB>(a, tile);
+    } else {
+        XRegs<M, NC, RB, CB> g;
+        x_load<M, NC, RB, CB>(a, tile, g);
+        x_store<M, NC, RB, CB>(a, g);
+        __syncthreads();
+        x_compute<M, NC, RB, CB>(a, tile);
+    }
 }
 
 template <typename M, int NC, int RB, int CB, int MAXT>

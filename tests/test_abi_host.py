@@ -330,6 +330,37 @@ def test_small_grid_default_tiles(etd):
         etd.etd_batch_destroy(b)
 
 
+def test_one_array_x_tile_default(etd):
+    """FP32-product, one-component plans whose x lines are too long for a
+    two-array tile of two line blocks default to the one-array (8, 2) tile;
+    it is valid nowhere else."""
+    for n, prec, want in (((1023, 100, 40), "fp32", (8, 2)), ((767, 64, 40), "fp32", (8, 2)),
+                          ((1023, 100, 40), "bf16x6", None), ((255, 100, 40), "fp32", None),
+                          ((511, 100, 40), "fp64_fp32", None)):
+        p = W.Problem(dim=3, n=n, kappa=(0.01,), tau=0.01, reaction="fisher", precision=prec)
+        plan = etd.etd_plan_create(p)
+        try:
+            x = etd.etd_plan_tiles(plan)[0]
+            if want:
+                assert x == want, (n, prec, x)
+            else:
+                assert x != (8, 2), (n, prec)
+                if prec != "bf16x6":
+                    with pytest.raises(etd.EtdError) as ei:
+                        etd.etd_plan_set_tiles(plan, [(8, 2)])
+                    assert ei.value.status == etd.ETD_EUNSUPPORTED
+        finally:
+            etd.etd_plan_destroy(plan)
+    p = W.Problem(dim=3, n=(1023, 100, 40), kappa=(0.01, 0.001), tau=0.01, reaction="fhn_cubic", precision="fp32")
+    plan = etd.etd_plan_create(p)
+    try:
+        with pytest.raises(etd.EtdError) as ei:
+            etd.etd_plan_set_tiles(plan, [(8, 2)])
+        assert ei.value.status == etd.ETD_EUNSUPPORTED
+    finally:
+        etd.etd_plan_destroy(plan)
+
+
 def test_bench_refuses_more_than_one_gpu():
     """The benchmark is a one-GPU measurement: --gpus above 1 exits with a
     message (before anything touches a device)."""

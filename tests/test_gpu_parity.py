@@ -481,3 +481,29 @@ def test_extreme_extents(etd, oracle_mod, precision, n):
     err = rel_l2(got, ref)
     print(f"  rel_l2={err:.3e}")
     assert err <= (FP64_TOL if precision == "fp64" else REDUCED_TOL)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+def test_one_array_x_tile_on_long_lines(etd, oracle_mod, precision):
+    """Lines of 1024 padded points whose two-array, two-block x tile exceeds
+    the LDS can take the one-array tile (eight row blocks per wave over two
+    line blocks, P w3 and P w4 in two passes): the same operations in the same
+    order, so bit-identical to the default tile, and within the reduced bar of
+    the oracle."""
+    import torch
+    p = W.Problem(dim=3, n=(1000, 40, 33), kappa=(0.02,), q=0.3, tau=0.002, reaction="fisher", precision=precision)
+    u0 = W.u0_random(p, seed=17, lo=0.0, hi=1.0)
+    outs = []
+    for tiles in (None, [(8, 2)]):
+        st = etd.Stepper(p)
+        if tiles:
+            st.set_tiles(tiles)
+            assert st.tiles()[0] == (8, 2)
+        u = st.field(u0)
+        st.advance(u, 4)
+        torch.cuda.synchronize()
+        outs.append(u.cpu().numpy().astype(np.float64))
+        st.close()
+    assert np.array_equal(outs[0], outs[1])
+    ref = oracle_mod.advance(p, u0, 4)
+    assert_close(outs[1], ref, REDUCED_TOL, precision)

@@ -330,6 +330,23 @@ def test_small_grid_default_tiles(etd):
         etd.etd_batch_destroy(b)
 
 
+def test_fp32_512_point_defaults(etd):
+    """FP32-product, one-component plans take four row blocks over two line
+    blocks in x stages of 512 padded points; outer stages of 512 points and
+    FP64 states keep their shapes."""
+    for n, prec, want in (((511, 100, 40), "fp32", [(4, 2), (2, 2), (2, 2)]),
+                          ((100, 64, 511), "fp32", [(2, 4), (2, 2), (2, 1)]),
+                          ((511, 100, 40), "fp64_fp32", [(2, 1), (2, 1), (2, 1)]),
+                          ((511, 100, 40), "fp64", [(2, 1), (1, 2), (1, 2)]),
+                          ((100, 64, 511), "fp64", [(1, 2), (1, 2), (2, 1)])):
+        p = W.Problem(dim=3, n=n, kappa=(0.01,), tau=0.01, reaction="fisher", precision=prec)
+        plan = etd.etd_plan_create(p)
+        try:
+            assert etd.etd_plan_tiles(plan) == want, (n, prec, etd.etd_plan_tiles(plan))
+        finally:
+            etd.etd_plan_destroy(plan)
+
+
 def test_one_array_x_tile_default(etd):
     """FP32-product, one-component plans whose x lines are too long for a
     two-array tile of two line blocks default to the one-array (8, 2) tile;

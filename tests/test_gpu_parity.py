@@ -507,3 +507,26 @@ def test_one_array_x_tile_on_long_lines(etd, oracle_mod, precision):
     assert np.array_equal(outs[0], outs[1])
     ref = oracle_mod.advance(p, u0, 4)
     assert_close(outs[1], ref, REDUCED_TOL, precision)
+
+
+def test_512_point_fp32_x_tile(etd, oracle_mod):
+    """FP32 x stages of 512 padded points default to four row blocks over two
+    line blocks in 512 threads: bit-identical to two row blocks over one block
+    in 1024 threads, and within the reduced bar of the oracle."""
+    import torch
+    p = W.Problem(dim=3, n=(511, 40, 33), kappa=(0.02,), q=0.3, tau=0.002, reaction="fisher", precision="fp32")
+    u0 = W.u0_random(p, seed=19, lo=0.0, hi=1.0)
+    outs = []
+    for tiles in (None, [(2, 1)]):
+        st = etd.Stepper(p)
+        if tiles:
+            st.set_tiles(tiles)
+        assert st.tiles()[0] == (tiles[0] if tiles else (4, 2))
+        u = st.field(u0)
+        st.advance(u, 4)
+        torch.cuda.synchronize()
+        outs.append(u.cpu().numpy().astype(np.float64))
+        st.close()
+    assert np.array_equal(outs[0], outs[1])
+    ref = oracle_mod.advance(p, u0, 4)
+    assert_close(outs[0], ref, REDUCED_TOL, "fp32")

@@ -15,11 +15,15 @@ namespace {
 // memory (L2-resident; M::a_off / a_kstep give a lane's first fragment and the
 // step to the next K block: row-major P, or a fragment-ordered copy)
 // and is held in a ring of PF register buffers, so each K block's fragment is
-// requested PF blocks before its use (PF = 1: one block ahead; launches with
-// one wave per SIMD need a deeper ring to cover the L2 latency, and there
-// FP64 B fragments are read from LDS one K block ahead as well); bload(q, k0)
-// returns the KL values of B fragment q for contracted indices k0 .. k0+KL of
-// this lane's column.
+// requested PF blocks before its use (launches with one wave per SIMD need a
+// deeper ring to cover the L2 latency, and there FP64 B fragments are read
+// from LDS one K block ahead as well).  With PF = 1 the compiler folds the
+// ring into loads at the top of each K block (the generated code waits for a
+// block's fragments as the block starts); the other waves on the SIMD cover
+// that latency, and keeping the loads a block ahead with a compiler memory
+// barrier measured slower in most stages, as the held fragments cost
+// registers.  bload(q, k0) returns the KL values of B fragment q for
+// contracted indices k0 .. k0+KL of this lane's column.
 template <typename M, int RB, int NQ, int PF = 1, typename BL>
 __device__ __forceinline__ void gemm(const void* __restrict__ P, int NP, int rb0, int li, int lg,
                                      vec_t<typename M::acc, 4> (&acc)[RB][NQ], BL bload) {

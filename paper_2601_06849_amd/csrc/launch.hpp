@@ -188,6 +188,14 @@ TileShape default_x_for(int NP, long nlines, long copies = 1) {
     // in 1024 threads; the 256-instance batch 15.1 -> 14.8 ms per step)
     if (sizeof(T) == 4 && !M::SPLIT_B && NC == 1 && NP == 512 && x_shape_ok<T, NC>(NP, nlines, TileShape{4, 2}))
         return TileShape{4, 2};
+    // batch groups of FP32 lines with fewer than 1024 four-block tiles take two
+    // line blocks: with so few large tiles the persistent launch ends on a
+    // ragged last round (96 instances of 255^2: 0.364 -> 0.335 ms per step,
+    // 48 of 127^2: 0.079 -> 0.067; single grids keep four, whose launches
+    // measured faster: the x stage of 255 x 127^2 0.107 against 0.116 ms)
+    if (sizeof(T) == 4 && !M::SPLIT_B && NC == 1 && copies > 1 && nlines / 64 * copies < 1024 &&
+        x_shape_ok<T, NC>(NP, nlines, TileShape{2, 2}))
+        return TileShape{2, 2};
     if (fp64_state_reduced<M>()) {
         if (!M::SPLIT_B && x_shape_ok<T, NC>(NP, nlines, TileShape{2, 2})) return TileShape{2, 2};
         if (x_shape_ok<T, NC>(NP, nlines, TileShape{2, 1})) return TileShape{2, 1};

@@ -347,6 +347,25 @@ def test_fp32_512_point_defaults(etd):
             etd.etd_plan_destroy(plan)
 
 
+def test_batch_fp32_x_tiles_follow_tile_count(etd):
+    """Batch groups of FP32 instances with fewer than 1024 four-block x tiles
+    take two line blocks; larger groups and single grids keep four."""
+    for n, count, want in ((255, 96, (2, 2)), (127, 48, (2, 2)), (255, 300, (2, 4))):
+        ps = [W.Problem(dim=2, n=(n, n), kappa=(0.01,), tau=0.01, reaction="fisher", precision="fp32")
+              for _ in range(count)]
+        b = etd.etd_batch_create(ps)
+        try:
+            assert etd.etd_batch_tiles(b, 0)[0] == want, (n, count, etd.etd_batch_tiles(b, 0))
+        finally:
+            etd.etd_batch_destroy(b)
+    p = W.Problem(dim=3, n=(255, 127, 127), kappa=(0.01,), tau=0.01, reaction="fisher", precision="fp32")
+    plan = etd.etd_plan_create(p)
+    try:
+        assert etd.etd_plan_tiles(plan)[0] == (2, 4)
+    finally:
+        etd.etd_plan_destroy(plan)
+
+
 def test_one_array_x_tile_default(etd):
     """FP32-product, one-component plans whose x lines are too long for a
     two-array tile of two line blocks default to the one-array (8, 2) tile;
